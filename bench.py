@@ -1,0 +1,177 @@
+"""Throughput of the shearing-box Poisson solve on one MI355X.
+
+Default workload: one 256^3 box (Lx = Ly = 4, Lz = 6, H = 1, z padded to 512, VGF-HybridBC),
+density = Gaussian stratification x (1 + 0.1 delta), delta a unit Gaussian random field with
+P(k) ~ k^-2; q = 1.5, Omega = 1, t = 0.3, G = 1.  A step is one full solve (remap, padded
+3-D transform, Green multiply, inverse, extraction) with rho and phi resident in HBM.
+
+Prints progress on stderr and ONE JSON line on stdout.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Poisson solves/s + HBM GB/s at 256^3 (FP32 vs FP64) at stated rel-L2 error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def time_plan(plan, rho, phi, shear, steps: int, warmup: int, profile: bool):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.solve(rho, phi, shear, stream=stream)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile_read()  # drop warm-up records
+        plan.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve(rho, phi, shear, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kernels = {}
+    if profile:
+        plan.profile_enable(False)
+        kernels = plan.profile_read()
+    return ms, kernels
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-samples", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2510_10070_amd import Box, Plan, Shear
+    from paper_2510_10070_amd.inputs import workload
+
+    w = workload("grf-256")
+    nx, ny, nz, lx, ly, lz = w["box"]
+    q, om, t, G = w["shear"]
+    shear = Shear(q, om, t, G)
+    log("generating the 256^3 random-field density")
+    rho64 = w["make"]()
+    N = nx * ny * nz
+    box = Box(nx, ny, nz, lx, ly, lz)
+
+    res = {}
+    phis = {}
+    for leg, prec, plain in (("fp32", "fp32", False), ("fp64", "fp64", False), ("plain_fp64", "fp64", True)):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        rho = torch.tensor(rho64, dtype=dt, device="cuda:0")
+        phi = torch.empty_like(rho)
+        plan = Plan(box, precision=prec, plain=plain)
+        steps = args.steps if not plain else max(10, args.steps // 4)
+        log(f"timing {leg}: {args.warmup} warm-up + {steps} steps")
+        ms, kern = time_plan(plan, rho, phi, shear, steps, args.warmup, profile=True)
+        w_bytes = 4 if prec == "fp32" else 8
+        b_alg = 6 * N * w_bytes  # rho in, 3 round trips of the half spectrum (N w bytes each), phi out
+        res[leg] = dict(ms=ms, solves_per_s=1e3 / ms, gbs_alg=b_alg / (ms * 1e-3) / 1e9, kernels=kern,
+                        describe=plan.describe(), steps=steps, w=w_bytes)
+        phis[leg] = (phi.double().cpu().numpy(), rho.double().cpu().numpy())
+        log(f"{leg}: {ms * 1e3:.1f} us/solve, {1e3 / ms:.0f} solves/s, {res[leg]['gbs_alg']:.0f} GB/s (algorithmic)")
+        plan.close()
+        del rho, phi
+        torch.cuda.empty_cache()
+
+    # accuracy against the FP64 CPU oracle, and the oracle's own throughput on this host
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        import oracle
+
+        ob = oracle.Box(nx, ny, nz, lx, ly, lz)
+        osh = oracle.Shear(q, om, t, G)
+        times = []
+        ref64 = None
+        for i in range(max(1, args.cpu_samples)):
+            log(f"oracle solve {i + 1} (FP64 input)")
+            t0 = time.perf_counter()
+            ref64 = oracle.solve(phis["fp64"][1], ob, osh)
+            times.append(time.perf_counter() - t0)
+        log("oracle solve on the FP32-rounded input")
+        t0 = time.perf_counter()
+        ref32 = oracle.solve(phis["fp32"][1], ob, osh)
+        times.append(time.perf_counter() - t0)
+        for leg, ref in (("fp32", ref32), ("fp64", ref64), ("plain_fp64", ref64)):
+            errs[leg] = float(np.linalg.norm(phis[leg][0] - ref) / np.linalg.norm(ref))
+        med = float(np.median(times))
+        cpu = {"value": 1.0 / med, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(times)} full 256^3 FP64 oracle solves (numpy, single thread), median {med:.2f} s"}
+
+    # roofline of the dominant kernel of the headline (FP32) leg
+    k = res["fp32"]["kernels"]
+    name, (launches, tot) = max(k.items(), key=lambda kv: kv[1][1])
+    avg_ms = tot / launches
+    per_launch_bytes = 2 * N * 4  # each pass reads and writes N*w bytes (rho/phi or the half spectrum)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "avg_us": round(avg_ms * 1e3, 2)}
+
+    head = res["fp32"]
+    out = {
+        "metric": METRIC,
+        "value": round(head["solves_per_s"], 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian random field x stratification)",
+        "config": {"workload": "grf-256: one 256x256x256 box, Lx=Ly=4, Lz=6, H=1, z padded to 512, VGF-HybridBC, "
+                               "q=1.5, Omega=1, t=0.3, G=1, FP32 bulk with FP64 Green/twiddles/k=0 pencil",
+                   "global_batch": 1, "seq_len": None, "parallelism": "single-gpu"},
+        "gbs_alg": round(head["gbs_alg"], 1),
+        "hbm_frac_alg": round(head["gbs_alg"] / HBM_PEAK_GBS, 4),
+        "rel_l2_vs_oracle": {k2: v for k2, v in errs.items()},
+        "fp64": {"solves_per_s": round(res["fp64"]["solves_per_s"], 1), "ms_per_step": round(res["fp64"]["ms"], 5),
+                 "gbs_alg": round(res["fp64"]["gbs_alg"], 1)},
+        "plain_fp64": {"solves_per_s": round(res["plain_fp64"]["solves_per_s"], 1),
+                       "ms_per_step": round(res["plain_fp64"]["ms"], 5)},
+        "speedup_vs_plain_fp64": {"fp32": round(head["solves_per_s"] / res["plain_fp64"]["solves_per_s"], 2),
+                                  "fp64": round(res["fp64"]["solves_per_s"] / res["plain_fp64"]["solves_per_s"], 2)},
+        "kernels_us": {leg: {kk: round(v[1] / v[0] * 1e3, 2) for kk, v in res[leg]["kernels"].items()} for leg in res},
+        "schedule": head["describe"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,264 @@
+// y passes of the streaming solve.
+//
+// Forward (steps a1 + a7): one workgroup per (x plane, chunk of ZC consecutive z cells).  The
+// real tile rho[x][0..Ny)[z0..z0+ZC) is read with z fastest; consecutive z pairs (z, z+1) are
+// packed as one complex column, so one complex length-Ny FFT transforms two real columns.
+// The two half spectra are separated, multiplied by the remap phase exp(-i Ky s x_i) that
+// maps the density to the shearing frame (Sect. 2.1), and stored for my < Ny/2 (the Nyquist
+// row is dropped).  For SASHA the workgroup also accumulates sum(rho) and sum(z rho) in double.
+//
+// Inverse (step a6, last part): the same tile shape in reverse: half spectra for my < Ny/2
+// times the reverse-mapping phase exp(+i Ky s x_i), rebuilt into two Hermitian columns packed
+// as one complex signal, one complex inverse FFT, real/imaginary parts written as z and z+1,
+// plus Phi_0(z) for SASHA.
+#include "fft_device.hpp"
+#include "sbp_internal.hpp"
+
+namespace sbp {
+
+// real z cells per tile (even); keeps the LDS tile at <= 32 KiB
+template <typename T, int N> constexpr int y_zc() {
+  return sizeof(T) == 4 ? (N <= 512 ? 16 : 8) : (N <= 512 ? 8 : 4);
+}
+constexpr int kYThreads = 256;
+
+// remap phase exp(-i 2 pi c) for c = my*(2x+1)*fy cycles, evaluated in double
+__device__ __forceinline__ void remap_phase(int my, int x, double fy, double& cs, double& sn) {
+  const double c = static_cast<double>(my * (2 * x + 1)) * fy;
+  const double r = c - floor(c);
+  double sv, cv;
+  sincospi(2.0 * r, &sv, &cv);
+  cs = cv;
+  sn = -sv;
+}
+
+template <typename T, int NY, bool REMAP = true>
+__global__ __launch_bounds__(kYThreads) void k_yfwd(const T* __restrict__ rho, cplx<T>* __restrict__ W,
+                                                    const cplx<T>* __restrict__ tw, const SolveScalars* __restrict__ sp,
+                                                    BoxGeom g, double* __restrict__ partials) {
+  constexpr int ZC = y_zc<T, NY>();
+  constexpr int NB = ZC / 2;  // complex columns
+  constexpr int NT = kYThreads;
+  __shared__ cplx<T> tile[NY * NB];
+  __shared__ cplx<T> ph[NY / 2];
+  __shared__ double red[2][NT / 64];
+
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x;
+  const int z0 = blockIdx.y * ZC;
+  const int nz = g.nz;
+  const int hy = NY / 2;
+
+  double s0 = 0.0, s1 = 0.0;
+  const double dz = g.lz / nz;
+  // load: NY rows of NB pairs, pairs fastest
+  for (int w = tid; w < NY * NB; w += NT) {
+    const int c = w % NB, y = w / NB;
+    const int z = z0 + 2 * c;
+    cplx<T> v = mk<T>(T(0), T(0));
+    if (z < nz) {
+      v = *reinterpret_cast<const cplx<T>*>(rho + ((size_t)x * NY + y) * nz + z);
+      if (partials) {
+        const double za = -0.5 * g.lz + (z + 0.5) * dz;
+        const double a = (double)v.x, b = (double)v.y;
+        s0 += a + b;
+        s1 += za * a + (za + dz) * b;
+      }
+    }
+    tile[y * NB + c] = v;
+  }
+  if (REMAP) {
+    const double fy = sp->fy;
+    for (int my = tid; my < hy; my += NT) {
+      double cs, sn;
+      remap_phase(my, x, fy, cs, sn);
+      ph[my] = mk<T>((T)cs, (T)sn);
+    }
+  }
+  if (partials) {
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_down(s0, o);
+      s1 += __shfl_down(s1, o);
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = s0;
+      red[1][tid >> 6] = s1;
+    }
+  }
+  __syncthreads();
+  if (partials && tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < NT / 64; ++i) {
+      a += red[0][i];
+      b += red[1][i];
+    }
+    const size_t slot = (size_t)blockIdx.y * g.nx + x;
+    partials[2 * slot] = a;
+    partials[2 * slot + 1] = b;
+  }
+
+  lds_fft<T, NY, Tile<NB, NB, 1, true>, NT, -1>(tile, tw, tid);
+
+  // separate the two real columns, remap, store my < NY/2
+  for (int w = tid; w < hy * NB; w += NT) {
+    const int c = w % NB, ky = w / NB;
+    const int z = z0 + 2 * c;
+    if (z >= nz) continue;
+    const cplx<T> c1 = tile[ky * NB + c];
+    const cplx<T> c2 = tile[((NY - ky) % NY) * NB + c];
+    cplx<T> a = mk<T>(T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y));
+    cplx<T> b = mk<T>(T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x));
+    if (REMAP) {
+      const cplx<T> p = ph[ky];
+      a = cmul<T>(a, p);
+      b = cmul<T>(b, p);
+    }
+    cplx<T>* dst = W + ((size_t)x * hy + ky) * nz + z;
+    dst[0] = a;
+    dst[1] = b;
+  }
+}
+
+template <typename T, int NY, bool REMAP = true>
+__global__ __launch_bounds__(kYThreads) void k_yinv(const cplx<T>* __restrict__ W, T* __restrict__ phi,
+                                                    const cplx<T>* __restrict__ tw, const SolveScalars* __restrict__ sp,
+                                                    BoxGeom g, const SashaCoef* __restrict__ coef) {
+  constexpr int ZC = y_zc<T, NY>();
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kYThreads;
+  __shared__ cplx<T> tile[NY * NB];
+  __shared__ cplx<T> ph[NY / 2];
+
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x;
+  const int z0 = blockIdx.y * ZC;
+  const int nz = g.nz;
+  const int hy = NY / 2;
+
+  if (REMAP) {
+    const double fy = sp->fy;
+    for (int my = tid; my < hy; my += NT) {
+      double cs, sn;
+      remap_phase(my, x, fy, cs, sn);
+      ph[my] = mk<T>((T)cs, (T)sn);  // exp(-i theta); used conjugated below
+    }
+  }
+  for (int c = tid; c < NB; c += NT) tile[hy * NB + c] = mk<T>(T(0), T(0));  // y Nyquist
+  __syncthreads();
+
+  for (int w = tid; w < hy * NB; w += NT) {
+    const int c = w % NB, ky = w / NB;
+    const int z = z0 + 2 * c;
+    cplx<T> a = mk<T>(T(0), T(0)), b = a;
+    if (z < nz) {
+      const cplx<T>* src = W + ((size_t)x * hy + ky) * nz + z;
+      a = src[0];
+      b = src[1];
+      if (REMAP) {
+        a = cmulc<T>(a, ph[ky]);
+        b = cmulc<T>(b, ph[ky]);
+      }
+    }
+    if (ky == 0) {
+      tile[c] = mk<T>(a.x, b.x);  // the DC terms of real columns are real
+    } else {
+      tile[ky * NB + c] = mk<T>(a.x - b.y, a.y + b.x);         // A + iB
+      tile[(NY - ky) * NB + c] = mk<T>(a.x + b.y, b.x - a.y);  // conj(A) + i conj(B)
+    }
+  }
+  __syncthreads();
+
+  lds_fft<T, NY, Tile<NB, NB, 1, true>, NT, +1>(tile, tw, tid);
+
+  const bool sasha = coef != nullptr;
+  double c2 = 0.0, c1 = 0.0;
+  if (sasha) {
+    c2 = coef->c2;
+    c1 = coef->c1;
+  }
+  const double dz = g.lz / nz;
+  for (int w = tid; w < NY * NB; w += NT) {
+    const int c = w % NB, y = w / NB;
+    const int z = z0 + 2 * c;
+    if (z >= nz) continue;
+    cplx<T> v = tile[y * NB + c];
+    if (sasha) {
+      const double za = -0.5 * g.lz + (z + 0.5) * dz;
+      const double zb = za + dz;
+      v.x = (T)((double)v.x + (c2 * za + c1) * za);
+      v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
+    }
+    *reinterpret_cast<cplx<T>*>(phi + ((size_t)x * NY + y) * nz + z) = v;
+  }
+}
+
+template <typename T, int NY>
+static hipError_t yfwd_t(const BoxGeom& g, const void* rho, void* W, const void* tw, const SolveScalars* sp,
+                         double* partials, hipStream_t st) {
+  constexpr int ZC = y_zc<T, NY>();
+  dim3 grid(g.nx, (g.nz + ZC - 1) / ZC);
+  hipLaunchKernelGGL((k_yfwd<T, NY>), grid, dim3(kYThreads), 0, st, (const T*)rho, (cplx<T>*)W,
+                     (const cplx<T>*)tw, sp, g, partials);
+  return hipGetLastError();
+}
+
+template <typename T, int NY>
+static hipError_t yinv_t(const BoxGeom& g, const void* W, void* phi, const void* tw, const SolveScalars* sp,
+                         const SashaCoef* coef, hipStream_t st) {
+  constexpr int ZC = y_zc<T, NY>();
+  dim3 grid(g.nx, (g.nz + ZC - 1) / ZC);
+  hipLaunchKernelGGL((k_yinv<T, NY>), grid, dim3(kYThreads), 0, st, (const cplx<T>*)W, (T*)phi,
+                     (const cplx<T>*)tw, sp, g, coef);
+  return hipGetLastError();
+}
+
+// plain path: y transforms without the remap (it runs as a separate kernel there)
+hipError_t launch_y_plain(int dir, const BoxGeom& g, const double* in, double* out, const void* tw_y, hipStream_t st) {
+#define SBP_CASE(N_)                                                                                       \
+  if (g.ny == N_) {                                                                                        \
+    constexpr int ZC = y_zc<double, N_>();                                                                 \
+    dim3 grid(g.nx, (g.nz + ZC - 1) / ZC);                                                                 \
+    if (dir < 0)                                                                                           \
+      hipLaunchKernelGGL((k_yfwd<double, N_, false>), grid, dim3(kYThreads), 0, st, in, (double2*)out,     \
+                         (const double2*)tw_y, (const SolveScalars*)nullptr, g, (double*)nullptr);         \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_yinv<double, N_, false>), grid, dim3(kYThreads), 0, st, (const double2*)in,    \
+                         out, (const double2*)tw_y, (const SolveScalars*)nullptr, g, (const SashaCoef*)nullptr); \
+    return hipGetLastError();                                                                              \
+  }
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  return hipErrorInvalidValue;
+}
+
+int yfwd_partials(int prec, const BoxGeom& g) {
+  int zc = 0;
+#define SBP_CASE(N_)                                             \
+  if (g.ny == N_) zc = prec ? y_zc<float, N_>() : y_zc<double, N_>();
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  if (zc == 0) return 0;
+  return g.nx * ((g.nz + zc - 1) / zc);
+}
+
+hipError_t launch_yfwd(int prec, const BoxGeom& g, const void* rho, void* W, const void* tw_y,
+                       const SolveScalars* sp, double* partials, hipStream_t st) {
+#define SBP_CASE(N_)                                                                  \
+  if (g.ny == N_) return prec ? yfwd_t<float, N_>(g, rho, W, tw_y, sp, partials, st) \
+                              : yfwd_t<double, N_>(g, rho, W, tw_y, sp, partials, st);
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_yinv(int prec, const BoxGeom& g, const void* W, void* phi, const void* tw_y,
+                       const SolveScalars* sp, const SashaCoef* coef, hipStream_t st) {
+#define SBP_CASE(N_)                                                             \
+  if (g.ny == N_) return prec ? yinv_t<float, N_>(g, W, phi, tw_y, sp, coef, st) \
+                              : yinv_t<double, N_>(g, W, phi, tw_y, sp, coef, st);
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sbp
