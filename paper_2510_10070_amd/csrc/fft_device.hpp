@@ -1,11 +1,14 @@
 // Device-side FFT building blocks for gfx950: complex helpers, radix-2/3/4/8 butterflies and
 // a Stockham auto-sort stage that transforms a batch of pencils held in LDS.
 //
-// A tile in LDS holds NB independent length-N transforms; element j of transform b lives at
-// buf[j*LD + b*BS].  Each Stockham stage with radix R reads R elements per butterfly at
-// stride N/R, applies twiddles exp(-+2 pi i k r/(Ns R)), runs the radix-R DFT and writes the
-// results at stride Ns, so the output is in natural order after the last stage.  Every
-// stage is read-all / barrier / write-all / barrier, so it works in place.
+// A tile in LDS holds NB independent length-N transforms; element j of transform b has the
+// logical index j*LD + b*BS.  The physical LDS slot is pad8(logical) = i + i/8: one spare
+// slot every eight elements breaks the power-of-two strides of the Stockham write pattern
+// that would otherwise hit the same LDS banks.  Each Stockham stage with radix R reads R
+// elements per butterfly at stride N/R, applies twiddles exp(-+2 pi i k r/(Ns R)), runs the
+// radix-R DFT and writes the results at stride Ns, so the output is in natural order after
+// the last stage.  Every stage is read-all / barrier / write-all / barrier, so it works in
+// place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,12 +35,12 @@ template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T>
 template <typename T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
   return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
-template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
-template <typename T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return mk<T>(a.x, -a.y); }
 // multiply by i*D (D = -1 forward, +1 inverse): i*(a+ib) = -b + ia
 template <int D, typename T> __device__ __forceinline__ cplx<T> rot(cplx<T> a) {
   return D < 0 ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
 }
+
+__host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
 
 // ------------------------------------------------------------------------------------------
 // Radix-R DFTs in registers.  D = -1: X_k = sum x_n exp(-2 pi i nk/R); D = +1: conjugate kernel.
@@ -126,16 +129,20 @@ SBP_SCHED(768, 8, 8, 4, 3)
 SBP_SCHED(1024, 8, 8, 4, 4)
 #undef SBP_SCHED
 
-// Tile layout: NB transforms, element (j, b) at j*LD + b*BS.  BFAST selects which index
-// consecutive threads walk (batch index for z-fastest tiles, element index otherwise), so
-// that neighbouring lanes touch neighbouring LDS words.
+// Tile layout: NB transforms, element (j, b) at logical index j*LD + b*BS, LDS slot pad8(.).
+// BFAST selects which index consecutive threads walk (batch index for z-fastest tiles,
+// element index otherwise), so that neighbouring lanes touch neighbouring LDS words.
 template <int NB_, int LD_, int BS_, bool BFAST_> struct Tile {
   static constexpr int NB = NB_, LD = LD_, BS = BS_;
   static constexpr bool BFAST = BFAST_;
+  static __device__ __forceinline__ int at(int j, int b) { return pad8(j * LD + b * BS); }
 };
 
+// LDS slots needed for a tile of n logical elements
+__host__ __device__ constexpr int lds_slots(int n) { return pad8(n - 1) + 1; }
+
 template <typename T, int N, int R, int NS, class L, int NT, int D>
-__device__ __forceinline__ void stockham_stage(cplx<T>* buf, const cplx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void stockham_stage(cplx<T>* buf, const cplx<T>* tw, int tid) {
   constexpr int NBF = N / R;
   constexpr int ITEMS = NBF * L::NB;
   constexpr int PER = (ITEMS + NT - 1) / NT;
@@ -147,7 +154,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, const cplx<T>* __re
       const int b = L::BFAST ? w % L::NB : w / NBF;
       const int j = L::BFAST ? w / L::NB : w % NBF;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[(j + r * NBF) * L::LD + b * L::BS];
+      for (int r = 0; r < R; ++r) v[p][r] = buf[L::at(j + r * NBF, b)];
     }
   }
   __syncthreads();
@@ -168,14 +175,14 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, const cplx<T>* __re
       Dft<R, D, T>::run(v[p]);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(base + r * NS) * L::LD + b * L::BS] = v[p][r];
+      for (int r = 0; r < R; ++r) buf[L::at(base + r * NS, b)] = v[p][r];
     }
   }
   __syncthreads();
 }
 
 template <typename T, int N, int S, int NS, class L, int NT, int D>
-__device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int tid) {
   if constexpr (S < Sched<N>::n) {
     constexpr int R = Sched<N>::r[S];
     stockham_stage<T, N, R, NS, L, NT, D>(buf, tw, tid);
@@ -183,11 +190,27 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* __restri
   }
 }
 
-// Transform all NB pencils of the tile in place.  tw[m] = exp(-2 pi i m/N), m < N.
-// D = -1 forward, +1 inverse (unnormalised).  Must be called by all NT threads.
+// Transform all NB pencils of the tile in place.  tw[m] = exp(-2 pi i m/N), m < N (in LDS or
+// global memory).  D = -1 forward, +1 inverse (unnormalised).  Called by all NT threads;
+// the tile must be complete (a barrier separates its producers from this call).
 template <typename T, int N, class L, int NT, int D>
-__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
   fft_stages<T, N, 0, 1, L, NT, D>(buf, tw, tid);
+}
+
+// copy the N-entry twiddle table into LDS
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src, int tid) {
+  for (int i = tid; i < N; i += NT) dst[i] = src[i];
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each XCD
+// a contiguous range of the T tiles so that tiles sharing cache lines run on the same L2 at
+// about the same time.
+__device__ __forceinline__ int xcd_tile(int b, int T) {
+  const int q = T >> 3, r = T & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
 }  // namespace sbp

@@ -14,9 +14,10 @@
 //                accurate tables, so no term cancels;
 //   VGF, k = 0:  (kz L sin(kz L) + cos(kz L) - 1) / kz^2, and L^2/2 at kz = 0;
 //   SASHA:       -1/(k^2 + kz^2), and 0 for the zero mode (mean subtraction, Sect. 2.2).
-// Float plans evaluate the per-pencil scalars in double and round them once; the k = 0 pencil
-// (the horizontally averaged density, which carries most of the potential) is transformed,
-// multiplied and transformed back entirely in double.
+// The per-pencil scalars (1 - E, E, 1/k, k^2, with the 4 pi G/(Nx Ny M) factor folded in) are
+// evaluated in double and rounded once.  Float plans transform, multiply and transform back
+// the k = 0 pencil (the horizontally averaged density, which carries most of the potential)
+// entirely in double.
 #include <type_traits>
 
 #include "fft_device.hpp"
@@ -30,8 +31,11 @@ template <typename T, int M> constexpr int z_pp() {
 }
 constexpr int kZThreads = 256;
 
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
 template <typename T, int M>
-__global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const cplx<T>* __restrict__ tw,
+__global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const cplx<T>* __restrict__ twg,
                                                  const double2* __restrict__ tw64, ZTables<T> zt, ZTables<double> zt64,
                                                  const SolveScalars* __restrict__ sp, BoxGeom g,
                                                  const double* __restrict__ partials, int npartials,
@@ -39,10 +43,13 @@ __global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const 
   constexpr int PP = z_pp<T, M>();
   constexpr int NT = kZThreads;
   constexpr bool kF32 = std::is_same<T, float>::value;
-  __shared__ cplx<T> tile[PP * M];
+  using L = Tile<PP, 1, M, false>;
+  using L1 = Tile<1, 1, M, false>;
+  __shared__ cplx<T> tile[lds_slots(PP * M)];
+  __shared__ cplx<T> tw[M];
   __shared__ T pa0[PP], pe[PP], pik[PP], pk2[PP];
   __shared__ int pzero[PP];
-  __shared__ double2 dbuf[kF32 ? M : 1];  // float plans: the k = 0 pencil in double
+  __shared__ double2 dbuf[kF32 ? lds_slots(M) : 1];  // float plans: the k = 0 pencil in double
 
   const int tid = threadIdx.x;
   const int hy = g.ny / 2;
@@ -53,19 +60,31 @@ __global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const 
   const bool sasha = g.method == 1;
   const double scale = sp->scale;
 
-  // contiguous load of nvalid pencils, then the zero padding
+  load_twiddles<T, M, NT>(tw, twg, tid);
+  // contiguous load of nvalid pencils (pairs of complex values: nz is even), then the padding
   const cplx<T>* src = W + (size_t)p0 * nz;
-  for (int w = tid; w < nvalid * nz; w += NT) {
-    const int p = w / nz, z = w - p * nz;
-    tile[p * M + z] = src[w];
+  for (int w = tid; w < nvalid * nz / 2; w += NT) {
+    const int e = 2 * w;
+    const int p = e / nz, z = e - p * nz;
+    cplx<T> v0, v1;
+    if constexpr (kF32) {
+      const float4 q = *reinterpret_cast<const float4*>(src + e);
+      v0 = mk<T>(q.x, q.y);
+      v1 = mk<T>(q.z, q.w);
+    } else {
+      v0 = src[e];
+      v1 = src[e + 1];
+    }
+    tile[L::at(z, p)] = v0;
+    tile[L::at(z + 1, p)] = v1;
   }
   for (int w = tid; w < PP * (M - nz); w += NT) {
     const int p = w / (M - nz), z = nz + (w - p * (M - nz));
-    tile[p * M + z] = mk<T>(T(0), T(0));
+    tile[L::at(z, p)] = mk<T>(T(0), T(0));
   }
   for (int w = tid; w < (PP - nvalid) * nz; w += NT) {
     const int p = nvalid + w / nz, z = w % nz;
-    tile[p * M + z] = mk<T>(T(0), T(0));
+    tile[L::at(z, p)] = mk<T>(T(0), T(0));
   }
   if (tid < PP) {
     const int q = p0 + tid;
@@ -80,8 +99,8 @@ __global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const 
     pzero[tid] = zero;
     pk2[tid] = (T)k2;
     if (!zero && !sasha) {
-      pa0[tid] = (T)(-expm1(-k * g.L));
-      pe[tid] = (T)exp(-k * g.L);
+      pa0[tid] = (T)(-expm1(-k * g.L) * scale);
+      pe[tid] = (T)(exp(-k * g.L) * scale);
       pik[tid] = (T)(1.0 / k);
     } else {
       pa0[tid] = T(0);
@@ -102,10 +121,10 @@ __global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const 
           v.x = (double)s0[z].x;
           v.y = (double)s0[z].y;
         }
-        dbuf[z] = v;
+        dbuf[L1::at(z, 0)] = v;
       }
       __syncthreads();
-      lds_fft<double, M, Tile<1, 1, M, false>, NT, -1>(dbuf, tw64, tid);
+      lds_fft<double, M, L1, NT, -1>(dbuf, tw64, tid);
       for (int mz = tid; mz < M; mz += NT) {
         double gk;
         if (sasha)
@@ -113,11 +132,11 @@ __global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const 
         else
           gk = mz == 0 ? 0.5 * g.L * g.L : (g.L * zt64.ks[mz] - zt64.s2[mz]) / zt64.kz2[mz];
         gk *= scale;
-        dbuf[mz].x *= gk;
-        dbuf[mz].y *= gk;
+        dbuf[L1::at(mz, 0)].x *= gk;
+        dbuf[L1::at(mz, 0)].y *= gk;
       }
       __syncthreads();
-      lds_fft<double, M, Tile<1, 1, M, false>, NT, +1>(dbuf, tw64, tid);
+      lds_fft<double, M, L1, NT, +1>(dbuf, tw64, tid);
     }
   }
 
@@ -155,36 +174,47 @@ __global__ __launch_bounds__(kZThreads) void k_z(cplx<T>* __restrict__ W, const 
   }
   __syncthreads();
 
-  lds_fft<T, M, Tile<PP, 1, M, false>, NT, -1>(tile, tw, tid);
+  lds_fft<T, M, L, NT, -1>(tile, tw, tid);
 
-  const T L = (T)g.L;
+  // Green multiply: each thread owns kz values and walks the pencils of the tile
+  const T L_ = (T)g.L;
   const T sc = (T)scale;
-  for (int w = tid; w < PP * M; w += NT) {
-    const int p = w / M, mz = w - p * M;
-    T gk;
-    if (sasha) {
-      gk = (pzero[p] && mz == 0) ? T(0) : T(-1) / (pk2[p] + zt.kz2[mz]);
-    } else if (!pzero[p]) {
-      gk = -(pa0[p] + pe[p] * (zt.s2[mz] + pik[p] * zt.ks[mz])) / (pk2[p] + zt.kz2[mz]);
-    } else {
-      gk = mz == 0 ? T(0.5) * L * L : (L * zt.ks[mz] - zt.s2[mz]) / zt.kz2[mz];
+  for (int mz = tid; mz < M; mz += NT) {
+    const T s2 = zt.s2[mz], ks = zt.ks[mz], kz2 = zt.kz2[mz];
+#pragma unroll 4
+    for (int p = 0; p < PP; ++p) {
+      T gk;
+      if (sasha) {
+        gk = (pzero[p] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[p] + kz2);
+      } else if (!pzero[p]) {
+        gk = -(pa0[p] + pe[p] * (s2 + pik[p] * ks)) * fast_rcp(pk2[p] + kz2);
+      } else {
+        gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
+      }
+      cplx<T>& v = tile[L::at(mz, p)];
+      v.x *= gk;
+      v.y *= gk;
     }
-    gk *= sc;
-    tile[w].x *= gk;
-    tile[w].y *= gk;
   }
   __syncthreads();
 
-  lds_fft<T, M, Tile<PP, 1, M, false>, NT, +1>(tile, tw, tid);
+  lds_fft<T, M, L, NT, +1>(tile, tw, tid);
 
   cplx<T>* dst = W + (size_t)p0 * nz;
-  for (int w = tid; w < nvalid * nz; w += NT) {
-    const int p = w / nz, z = w - p * nz;
-    cplx<T> v = tile[p * M + z];
+  for (int w = tid; w < nvalid * nz / 2; w += NT) {
+    const int e = 2 * w;
+    const int p = e / nz, z = e - p * nz;
+    cplx<T> v0 = tile[L::at(z, p)], v1 = tile[L::at(z + 1, p)];
     if constexpr (kF32) {
-      if (blockIdx.x == 0 && p == 0) v = mk<T>((T)dbuf[z].x, (T)dbuf[z].y);
+      if (blockIdx.x == 0 && p == 0) {
+        v0 = mk<T>((T)dbuf[L1::at(z, 0)].x, (T)dbuf[L1::at(z, 0)].y);
+        v1 = mk<T>((T)dbuf[L1::at(z + 1, 0)].x, (T)dbuf[L1::at(z + 1, 0)].y);
+      }
+      *reinterpret_cast<float4*>(dst + e) = make_float4(v0.x, v0.y, v1.x, v1.y);
+    } else {
+      dst[e] = v0;
+      dst[e + 1] = v1;
     }
-    dst[w] = v;
   }
 }
 

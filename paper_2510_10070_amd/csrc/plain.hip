@@ -151,14 +151,16 @@ template <int M> constexpr int zplain_pp() {
 template <int M, int D>
 __global__ __launch_bounds__(256) void k_plain_zfft(double2* __restrict__ P, const double2* __restrict__ tw, int npencils) {
   constexpr int PP = zplain_pp<M>();
-  __shared__ double2 tile[PP * M];
+  using L = Tile<PP, 1, M, false>;
+  __shared__ double2 tile[lds_slots(PP * M)];
   const int p0 = blockIdx.x * PP;
   const int nvalid = min(PP, npencils - p0);
   double2* base = P + (size_t)p0 * M;
-  for (int w = threadIdx.x; w < PP * M; w += 256) tile[w] = w < nvalid * M ? base[w] : make_double2(0.0, 0.0);
+  for (int w = threadIdx.x; w < PP * M; w += 256)
+    tile[L::at(w % M, w / M)] = w < nvalid * M ? base[w] : make_double2(0.0, 0.0);
   __syncthreads();
-  lds_fft<double, M, Tile<PP, 1, M, false>, 256, D>(tile, tw, threadIdx.x);
-  for (int w = threadIdx.x; w < nvalid * M; w += 256) base[w] = tile[w];
+  lds_fft<double, M, L, 256, D>(tile, tw, threadIdx.x);
+  for (int w = threadIdx.x; w < nvalid * M; w += 256) base[w] = tile[L::at(w % M, w / M)];
 }
 
 hipError_t launch_zfft_plain(int dir, const BoxGeom& g, double* P, const void* tw_m, hipStream_t st) {
