@@ -63,6 +63,10 @@ typedef enum { SBP_VGF = 0, SBP_SASHA = 1 } sbp_method;
 #define SBP_FLAG_AUTOTUNE 0x2u /* time the tile variants at plan creation and keep the fastest */
 #define SBP_FLAG_PLAIN 0x4u    /* unfused reference path: padded spectrum in HBM, one kernel per
                                   step (pad, each axis transform, Green multiply, extract, ...) */
+#define SBP_FLAG_FIVE_PASS 0x8u /* one streaming pass per axis and direction (five HBM round trips
+                                   of the half spectrum) even where the fused three-pass schedule
+                                   applies (power-of-two 16 <= nx <= 256, 16 <= ny <= 512,
+                                   32 <= pad*nz <= 512) */
 
 /* Geometry and method of one box.
  *   nx, ny: horizontal cells, each in {8,12,16,24,32,48,64,96,128,192,256,384,512,768,1024};

@@ -1,14 +1,23 @@
-// Device-side FFT building blocks for gfx950: complex helpers, radix-2/3/4/8 butterflies and
-// a Stockham auto-sort stage that transforms a batch of pencils held in LDS.
+// Device-side FFT engine for gfx950: complex helpers, radix-2/3/4/8 butterflies and a
+// register-resident Stockham auto-sort schedule whose stages exchange data through LDS.
 //
-// A tile in LDS holds NB independent length-N transforms; element j of transform b has the
-// logical index j*LD + b*BS.  The physical LDS slot is pad8(logical) = i + i/8: one spare
-// slot every eight elements breaks the power-of-two strides of the Stockham write pattern
-// that would otherwise hit the same LDS banks.  Each Stockham stage with radix R reads R
-// elements per butterfly at stride N/R, applies twiddles exp(-+2 pi i k r/(Ns R)), runs the
-// radix-R DFT and writes the results at stride Ns, so the output is in natural order after
-// the last stage.  Every stage is read-all / barrier / write-all / barrier, so it works in
-// place.
+// A tile holds NB independent length-N transforms; element j of transform b has the logical
+// index j*LD + b*BS and the LDS slot pad8(logical) = i + i/8 (one spare slot every eight
+// elements breaks the power-of-two strides of the Stockham write pattern, which would
+// otherwise land on the same LDS banks).
+//
+// Stage s of radix R (Ns = product of the earlier radices) takes, for butterfly j of
+// transform b, the R inputs j + r N/R, applies the twiddles exp(-+2 pi i k r/(Ns R)),
+// k = j mod Ns, runs the radix-R DFT and produces the outputs base + r Ns,
+// base = (j - k) R + k; after the last stage the transform is in natural order.
+//
+// Each thread keeps its butterflies in registers.  The first stage reads its inputs through
+// a caller functor (straight from HBM, from LDS or from registers) and the last stage hands
+// its outputs to a caller functor (straight to HBM, or to LDS), so a transform costs only
+// (stages - 1) LDS exchanges.  A forward transform whose last radix equals the first radix
+// of the inverse schedule can hand its outputs to the inverse in registers: the outputs
+// j + r Ns of the last forward stage are exactly the inputs j + r N/R of the first inverse
+// stage, held by the same thread.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,6 +50,15 @@ template <int D, typename T> __device__ __forceinline__ cplx<T> rot(cplx<T> a) {
 }
 
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
+// LDS slots needed for a tile of n logical elements
+__host__ __device__ constexpr int lds_slots(int n) { return pad8(n - 1) + 1; }
+// pad8(a + C) from pa = pad8(a): exact shift when C is a multiple of 8
+template <int C> __device__ __forceinline__ int pad_add(int pa, int a) {
+  if constexpr (C % 8 == 0)
+    return pa + C + C / 8;
+  else
+    return pad8(a + C);
+}
 
 // ------------------------------------------------------------------------------------------
 // Radix-R DFTs in registers.  D = -1: X_k = sum x_n exp(-2 pi i nk/R); D = +1: conjugate kernel.
@@ -103,99 +121,299 @@ template <int D, typename T> struct Dft<8, D, T> {
   }
 };
 
-// ------------------------------------------------------------------------------------------
-// Radix schedules per transform length (product of the radices = N).
+template <int D, typename T> struct Dft<1, D, T> {
+  static __device__ __forceinline__ void run(cplx<T>*) {}
+};
 
-template <int N> struct Sched;
-#define SBP_SCHED(N_, ...)                                   \
-  template <> struct Sched<N_> {                             \
-    static constexpr int r[] = {__VA_ARGS__};                \
-    static constexpr int n = sizeof(r) / sizeof(int);        \
-  };
-SBP_SCHED(8, 8)
-SBP_SCHED(12, 4, 3)
-SBP_SCHED(16, 4, 4)
-SBP_SCHED(24, 8, 3)
-SBP_SCHED(32, 8, 4)
-SBP_SCHED(48, 4, 4, 3)
-SBP_SCHED(64, 8, 8)
-SBP_SCHED(96, 8, 4, 3)
-SBP_SCHED(128, 8, 4, 4)
-SBP_SCHED(192, 8, 8, 3)
-SBP_SCHED(256, 8, 8, 4)
-SBP_SCHED(384, 8, 4, 4, 3)
-SBP_SCHED(512, 8, 8, 8)
-SBP_SCHED(768, 8, 8, 4, 3)
-SBP_SCHED(1024, 8, 8, 4, 4)
-#undef SBP_SCHED
+// 16 = 4 x 4: inner DFT4 over n1 (stride 4), twiddles w16^(n2 k1), outer DFT4 over n2
+template <int D, typename T> struct Dft<16, D, T> {
+  static __device__ __forceinline__ cplx<T> twc(cplx<T> a, T c, T s) {  // a * (c + i D s)
+    return mk<T>(a.x * c - D * a.y * s, a.y * c + D * a.x * s);
+  }
+  static __device__ __forceinline__ void run(cplx<T>* v) {
+    const T c1 = T(0.92387953251128675612818318939679);  // cos(pi/8)
+    const T s1 = T(0.38268343236508977172845998403040);  // sin(pi/8)
+    const T c2 = T(0.70710678118654752440084436210485);  // cos(pi/4)
+    cplx<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cplx<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<4, D, T>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+    }
+    // w^(n2 k1): (1,1)->w1 (1,2)->w2 (1,3)->w3 (2,1)->w2 (2,2)->w4 (2,3)->w6 (3,1)->w3 (3,2)->w6 (3,3)->w9
+    y[1][1] = twc(y[1][1], c1, s1);
+    y[1][2] = twc(y[1][2], c2, c2);
+    y[1][3] = twc(y[1][3], s1, c1);
+    y[2][1] = twc(y[2][1], c2, c2);
+    y[2][2] = rot<D, T>(y[2][2]);
+    y[2][3] = twc(y[2][3], -c2, c2);
+    y[3][1] = twc(y[3][1], s1, c1);
+    y[3][2] = twc(y[3][2], -c2, c2);
+    y[3][3] = twc(y[3][3], -c1, -s1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cplx<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<4, D, T>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
+// ------------------------------------------------------------------------------------------
+// Radix schedules.  Fwd<N> is the forward schedule; Inv<N> is its reverse, so the first
+// inverse radix equals the last forward radix (register hand-off).
+
+template <int... Rs> struct RList {
+  static constexpr int n = sizeof...(Rs);
+  static constexpr int r[] = {Rs...};
+  static constexpr int ns(int s) {
+    int v = 1;
+    for (int i = 0; i < s; ++i) v *= r[i];
+    return v;
+  }
+};
+template <int N> struct Fwd;
+template <int N> struct Inv;
+template <> struct Fwd<8> { using L = RList<8>; };
+template <> struct Inv<8> { using L = RList<8>; };
+template <> struct Fwd<12> { using L = RList<4, 3>; };
+template <> struct Inv<12> { using L = RList<3, 4>; };
+template <> struct Fwd<16> { using L = RList<4, 4>; };
+template <> struct Inv<16> { using L = RList<4, 4>; };
+template <> struct Fwd<24> { using L = RList<8, 3>; };
+template <> struct Inv<24> { using L = RList<3, 8>; };
+template <> struct Fwd<32> { using L = RList<8, 4>; };
+template <> struct Inv<32> { using L = RList<4, 8>; };
+template <> struct Fwd<48> { using L = RList<4, 4, 3>; };
+template <> struct Inv<48> { using L = RList<3, 4, 4>; };
+template <> struct Fwd<64> { using L = RList<8, 8>; };
+template <> struct Inv<64> { using L = RList<8, 8>; };
+template <> struct Fwd<96> { using L = RList<8, 4, 3>; };
+template <> struct Inv<96> { using L = RList<3, 4, 8>; };
+template <> struct Fwd<128> { using L = RList<8, 4, 4>; };
+template <> struct Inv<128> { using L = RList<4, 4, 8>; };
+template <> struct Fwd<192> { using L = RList<8, 8, 3>; };
+template <> struct Inv<192> { using L = RList<3, 8, 8>; };
+template <> struct Fwd<256> { using L = RList<8, 8, 4>; };
+template <> struct Inv<256> { using L = RList<4, 8, 8>; };
+template <> struct Fwd<384> { using L = RList<8, 4, 4, 3>; };
+template <> struct Inv<384> { using L = RList<3, 4, 4, 8>; };
+template <> struct Fwd<512> { using L = RList<8, 8, 8>; };
+template <> struct Inv<512> { using L = RList<8, 8, 8>; };
+template <> struct Fwd<768> { using L = RList<8, 8, 4, 3>; };
+template <> struct Inv<768> { using L = RList<3, 4, 8, 8>; };
+template <> struct Fwd<1024> { using L = RList<8, 8, 4, 4>; };
+template <> struct Inv<1024> { using L = RList<4, 4, 8, 8>; };
 
 // Tile layout: NB transforms, element (j, b) at logical index j*LD + b*BS, LDS slot pad8(.).
 // BFAST selects which index consecutive threads walk (batch index for z-fastest tiles,
-// element index otherwise), so that neighbouring lanes touch neighbouring LDS words.
+// element index otherwise), so that neighbouring lanes touch neighbouring words.
 template <int NB_, int LD_, int BS_, bool BFAST_> struct Tile {
   static constexpr int NB = NB_, LD = LD_, BS = BS_;
   static constexpr bool BFAST = BFAST_;
+  static __device__ __forceinline__ int logical(int j, int b) { return j * LD + b * BS; }
   static __device__ __forceinline__ int at(int j, int b) { return pad8(j * LD + b * BS); }
 };
 
-// LDS slots needed for a tile of n logical elements
-__host__ __device__ constexpr int lds_slots(int n) { return pad8(n - 1) + 1; }
+// One Stockham stage of schedule RL for a tile L processed by NT threads.
+template <typename T, int N, class RL, int S, class L, int NT, int D> struct Stage {
+  static constexpr int R = RL::r[S];
+  static constexpr int NS = RL::ns(S);
+  static constexpr int NBF = N / R;
+  static constexpr int ITEMS = NBF * L::NB;
+  static constexpr int PER = (ITEMS + NT - 1) / NT;
+  static constexpr bool FULL = ITEMS % NT == 0;
 
-template <typename T, int N, int R, int NS, class L, int NT, int D>
-__device__ __forceinline__ void stockham_stage(cplx<T>* buf, const cplx<T>* tw, int tid) {
-  constexpr int NBF = N / R;
-  constexpr int ITEMS = NBF * L::NB;
-  constexpr int PER = (ITEMS + NT - 1) / NT;
-  cplx<T> v[PER][R];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
+  static __device__ __forceinline__ bool item(int tid, int p, int& j, int& b) {
     const int w = tid + p * NT;
-    if (ITEMS % NT == 0 || w < ITEMS) {
-      const int b = L::BFAST ? w % L::NB : w / NBF;
-      const int j = L::BFAST ? w / L::NB : w % NBF;
+    if constexpr (L::BFAST) {
+      b = w % L::NB;
+      j = w / L::NB;
+    } else {
+      j = w % NBF;
+      b = w / NBF;
+    }
+    return FULL || w < ITEMS;
+  }
+  // inputs j + r NBF from a functor f(elem, b); inputs r >= RIN are known zeros
+  template <int RIN = R, class F>
+  static __device__ __forceinline__ void read_fn(cplx<T> (&v)[PER][R], int tid, F&& f) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[L::at(j + r * NBF, b)];
+    for (int p = 0; p < PER; ++p) {
+      int j, b;
+      if (item(tid, p, j, b)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = r < RIN ? f(j + r * NBF, b) : mk<T>(T(0), T(0));
+      }
     }
   }
-  __syncthreads();
+  static __device__ __forceinline__ void read_lds(cplx<T> (&v)[PER][R], const cplx<T>* buf, int tid) {
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int w = tid + p * NT;
-    if (ITEMS % NT == 0 || w < ITEMS) {
-      const int b = L::BFAST ? w % L::NB : w / NBF;
-      const int j = L::BFAST ? w / L::NB : w % NBF;
-      const int k = j % NS;
-      if constexpr (NS > 1) {
+    for (int p = 0; p < PER; ++p) {
+      int j, b;
+      if (item(tid, p, j, b)) {
+        const int a = L::logical(j, b);
+        const int pa = pad8(a);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cplx<T> t = tw[k * r * (N / (NS * R))];
-          v[p][r] = D < 0 ? cmul<T>(v[p][r], t) : cmulc<T>(v[p][r], t);
+        for (int r = 0; r < R; ++r) v[p][r] = buf[pad_off<NBF * L::LD>(pa, a, r)];
+      }
+    }
+  }
+  // stride-C offset r*C from the padded base
+  template <int C> static __device__ __forceinline__ int pad_off(int pa, int a, int r) {
+    if constexpr (C % 8 == 0)
+      return pa + r * (C + C / 8);
+    else
+      return pad8(a + r * C);
+  }
+  static __device__ __forceinline__ void twiddle_dft(cplx<T> (&v)[PER][R], const cplx<T>* tw, int tid) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      int j, b;
+      if (item(tid, p, j, b)) {
+        if constexpr (NS > 1) {
+          const int k = j % NS;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const cplx<T> t = tw[k * r * (N / (NS * R))];
+            v[p][r] = D < 0 ? cmul<T>(v[p][r], t) : cmulc<T>(v[p][r], t);
+          }
+        }
+        Dft<R, D, T>::run(v[p]);
+      }
+    }
+  }
+  // outputs base + r NS to a functor f(elem, b, value); outputs r >= ROUT are not needed
+  template <int ROUT = R, class F>
+  static __device__ __forceinline__ void write_fn(cplx<T> (&v)[PER][R], int tid, F&& f) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      int j, b;
+      if (item(tid, p, j, b)) {
+        const int k = j % NS;
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < ROUT; ++r) f(base + r * NS, b, v[p][r]);
+      }
+    }
+  }
+  static __device__ __forceinline__ void write_lds(cplx<T> (&v)[PER][R], cplx<T>* buf, int tid) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      int j, b;
+      if (item(tid, p, j, b)) {
+        const int k = j % NS;
+        const int base = (j - k) * R + k;
+        const int a = L::logical(base, b);
+        if constexpr ((NS * L::LD) % 8 == 0) {
+          const int pa = pad8(a);
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + (NS * L::LD) / 8)] = v[p][r];
+        } else if constexpr (NS == 1 && R == 8 && L::LD == 1 && (L::BS % 8 == 0 || L::NB == 1)) {
+          // base = 8j: a multiple of 8, so the eight outputs share one pad shift
+          const int pa = pad8(a);
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[pa + r] = v[p][r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[pad8(a + r * NS * L::LD)] = v[p][r];
         }
       }
-      Dft<R, D, T>::run(v[p]);
-      const int base = (j - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[L::at(base + r * NS, b)] = v[p][r];
     }
   }
-  __syncthreads();
-}
+};
 
-template <typename T, int N, int S, int NS, class L, int NT, int D>
-__device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int tid) {
-  if constexpr (S < Sched<N>::n) {
-    constexpr int R = Sched<N>::r[S];
-    stockham_stage<T, N, R, NS, L, NT, D>(buf, tw, tid);
-    fft_stages<T, N, S + 1, NS * R, L, NT, D>(buf, tw, tid);
+// Full transform of every pencil in the tile.
+//   src(elem, b) -> cplx: input element of transform b (read by stage 0 only);
+//   dst(elem, b, v): output element of transform b (written by the last stage only).
+// `buf` is the LDS exchange tile (lds_slots(N*LD*NB) slots for the layout L).  SRC_LDS: src
+// reads `buf`; DST_LDS: dst writes `buf`.  Barriers separate every read of `buf` from the
+// next write to it.  On return without DST_LDS the last stage has read `buf`: the caller must
+// barrier before writing it again; with DST_LDS the caller must barrier before reading it.
+template <typename T, int N, class RL, class L, int NT, int D, bool SRC_LDS, bool DST_LDS, int S = 0, int Q = 1,
+          class Src, class Dst>
+__device__ __forceinline__ void fft_run(cplx<T>* buf, const cplx<T>* tw, int tid, Src&& src, Dst&& dst) {
+  using St = Stage<T, N, RL, S, L, NT, D>;
+  constexpr bool LAST = S == RL::n - 1;
+  cplx<T> v[St::PER][St::R];
+  if constexpr (S == 0) {
+    St::read_fn(v, tid, src);
+    if constexpr (SRC_LDS && (!LAST || DST_LDS)) __syncthreads();
+  } else {
+    St::read_lds(v, buf, tid);
+    if constexpr (!LAST || DST_LDS) __syncthreads();
+  }
+  St::twiddle_dft(v, tw, tid);
+  if constexpr (LAST) {
+    // with Q > 1 only the outputs below N/Q are wanted: r < R/Q when the radix divides
+    St::template write_fn<(St::R % Q == 0) ? St::R / Q : St::R>(v, tid, dst);
+  } else {
+    St::write_lds(v, buf, tid);
+    __syncthreads();
+    fft_run<T, N, RL, L, NT, D, SRC_LDS, DST_LDS, S + 1, Q>(buf, tw, tid, src, dst);
   }
 }
 
-// Transform all NB pencils of the tile in place.  tw[m] = exp(-2 pi i m/N), m < N (in LDS or
-// global memory).  D = -1 forward, +1 inverse (unnormalised).  Called by all NT threads;
-// the tile must be complete (a barrier separates its producers from this call).
-template <typename T, int N, class L, int NT, int D>
-__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
-  fft_stages<T, N, 0, 1, L, NT, D>(buf, tw, tid);
+// Forward transform, pointwise op, inverse transform, with the hand-off between the last
+// forward stage and the first inverse stage kept in registers.
+//   src(elem, b) -> cplx (forward inputs), op(elem, b, cplx&) on spectrum values,
+//   dst(elem, b, v) (inverse outputs).
+// Q > 1 (zero padding by Q): forward inputs at or above N/Q are zero and inverse outputs at or
+// above N/Q are discarded; both are dropped at compile time where the radix allows.
+template <typename T, int N, class L, int NT, int S, int Q = 1, class Src, class Op, class Dst>
+__device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, int tid, Src&& src, Op&& op,
+                                               Dst&& dst) {
+  using RF = typename Fwd<N>::L;
+  using RI = typename Inv<N>::L;
+  static_assert(RF::r[RF::n - 1] == RI::r[0], "hand-off needs matching radices");
+  if constexpr (S < RF::n - 1) {
+    // forward stages before the last one
+    using St = Stage<T, N, RF, S, L, NT, -1>;
+    cplx<T> v[St::PER][St::R];
+    if constexpr (S == 0) {
+      St::template read_fn<(St::R % Q == 0) ? St::R / Q : St::R>(v, tid, src);
+    } else {
+      St::read_lds(v, buf, tid);
+      __syncthreads();
+    }
+    St::twiddle_dft(v, tw, tid);
+    St::write_lds(v, buf, tid);
+    __syncthreads();
+    fft_fwd_op_inv<T, N, L, NT, S + 1, Q>(buf, tw, tid, src, op, dst);
+  } else {
+    using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
+    using Si = Stage<T, N, RI, 0, L, NT, +1>;
+    static_assert(Sf::PER == Si::PER && Sf::R == Si::R, "stage shapes must agree");
+    cplx<T> v[Sf::PER][Sf::R];
+    if constexpr (RF::n == 1) {
+      Sf::template read_fn<(Sf::R % Q == 0) ? Sf::R / Q : Sf::R>(v, tid, src);
+    } else {
+      Sf::read_lds(v, buf, tid);
+      __syncthreads();
+    }
+    Sf::twiddle_dft(v, tw, tid);
+    // last forward stage: outputs j + r*NBF (base = j since j < NS = NBF)
+#pragma unroll
+    for (int p = 0; p < Sf::PER; ++p) {
+      int j, b;
+      if (Sf::item(tid, p, j, b)) {
+#pragma unroll
+        for (int r = 0; r < Sf::R; ++r) op(j + r * Sf::NBF, b, v[p][r]);
+      }
+    }
+    // first inverse stage on the same registers (Ns = 1: no twiddles)
+    Si::twiddle_dft(v, tw, tid);
+    if constexpr (RI::n == 1) {
+      Si::template write_fn<(Si::R % Q == 0) ? Si::R / Q : Si::R>(v, tid, dst);
+    } else {
+      Si::write_lds(v, buf, tid);
+      __syncthreads();
+      fft_run<T, N, RI, L, NT, +1, false, false, 1, Q>(buf, tw, tid, src, dst);
+    }
+  }
 }
 
 // copy the N-entry twiddle table into LDS
@@ -211,6 +429,16 @@ __device__ __forceinline__ int xcd_tile(int b, int T) {
   const int q = T >> 3, r = T & 7;
   const int xcd = b & 7, slot = b >> 3;
   return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+// Legacy in-place transform of a full LDS tile (both ends in LDS): used by small helpers.
+template <typename T, int N, class L, int NT, int D>
+__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
+  using RL = typename Fwd<N>::L;
+  fft_run<T, N, RL, L, NT, D, true, true>(
+      buf, tw, tid, [&](int e, int b) { return buf[L::at(e, b)]; },
+      [&](int e, int b, cplx<T> v) { buf[L::at(e, b)] = v; });
+  __syncthreads();
 }
 
 }  // namespace sbp

@@ -1,0 +1,519 @@
+// Fused three-pass schedule: the half spectrum crosses HBM three times (rho -> W, W -> W,
+// W -> phi) instead of five.  The x transform of length Nx = A*B is split four-step:
+//   X[k1 + A k2] = sum_j w_B^(j k2) [ w_Nx^(j k1) sum_a x[j + B a] w_A^(a k1) ]
+// Pass A does, for B-strided x planes {j + B a}, the y transform and remap of every plane and
+// the A-point DFT across the planes in registers (plus the w_Nx^(j k1) twiddle).  Pass B does,
+// for each (k1, my), the B-point DFT across j in registers, the padded z transform with the
+// Green multiply for every Kx = k1 + A k2, and the inverse B-point DFT.  Pass C inverts pass A.
+//
+// Intermediate layout: W[k1][my][j][z] (complex, k1 < A, my < Ny/2, j < B, z < Nz), so the B
+// pencils that pass B needs for one (k1, my) are one contiguous run of B*Nz values.
+#pragma once
+
+#include "passes.hpp"
+
+namespace sbp {
+
+constexpr int kFusedAC = 512;  // threads of passes A and C
+constexpr int kFusedB = 256;   // threads of pass B
+
+// real z cells per pass-A/C tile: variant 1 = 64-byte rows, variant 0 = 32-byte rows
+template <typename T, int V> constexpr int fa_zc() { return (V ? 64 : 32) / (int)sizeof(T); }
+// pencils per z-transform group in pass B (LDS budget)
+template <typename T, int M, int B> constexpr int fb_group() {
+  constexpr int g = 2048 / M;  // enough butterflies to keep all 256 threads busy
+  return g >= B ? B : (g < 1 ? 1 : g);
+}
+
+// four-step split used by the fused schedule: B = 16 pencils per pass-B block, A = Nx/16
+constexpr int kFusedB16 = 16;
+inline bool fused_supported(int nx, int ny, int m) {
+  auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
+  return pow2(nx) && nx >= 16 && nx <= 256 && pow2(ny) && ny >= 16 && ny <= 512 && pow2(m) && m >= 32 &&
+         m <= 512;
+}
+
+// remap phase of plane x = j + B a as P_j Q^a in double: exp(-i 2 pi my (2x+1) fy)
+struct PlanePhase {
+  double pr, pi, qr, qi;  // current phase and the per-plane step
+  __device__ __forceinline__ void init(int my, int j, int B, double fy) {
+    double s, c;
+    const double c0 = static_cast<double>(my * (2 * j + 1)) * fy;
+    sincospi(2.0 * (c0 - floor(c0)), &s, &c);
+    pr = c;
+    pi = -s;
+    const double c1 = static_cast<double>(my) * (2.0 * B) * fy;
+    sincospi(2.0 * (c1 - floor(c1)), &s, &c);
+    qr = c;
+    qi = -s;
+  }
+  __device__ __forceinline__ void step() {
+    const double r = pr * qr - pi * qi;
+    pi = pr * qi + pi * qr;
+    pr = r;
+  }
+};
+
+// ------------------------------------------------------------------------------------------
+// Pass A: one block per (j, z chunk).  The A planes x = j + B a go through the y transform in
+// groups of PG, each plane handled by NT/PG threads with its own LDS tile; every thread then
+// keeps the remapped half spectra of its positions for all A planes in registers.  Finally the
+// A-point DFT across planes, the w_Nx^(j k1) twiddle and the store to W[k1][my][j][z].
+
+template <typename T, int NY, int A, int B, int V>
+__global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                 const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+  constexpr int ZC = fa_zc<T, V>();
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kFusedAC;
+  constexpr int PG = A < 4 ? A : 4;  // planes transformed side by side
+  constexpr int TNT = NT / PG;       // threads per plane transform
+  constexpr int HY = NY / 2;
+  constexpr int QN = HY * NB;        // output positions (ky, c) of one plane
+  constexpr int POS = (QN + NT - 1) / NT;
+  constexpr int SLOTS = lds_slots(NY * NB);
+  using L = Tile<NB, NB, 1, true>;
+  __shared__ cplx<T> tile[PG * SLOTS];
+  __shared__ cplx<T> tw[NY];
+  __shared__ double red[2][NT / 64];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int sub = tid / TNT, stid = tid - sub * TNT;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int j = t / nzc;
+  const int z0 = (t - j * nzc) * ZC;
+  const int zn = min(ZC, nz - z0);
+  const T* rho = static_cast<const T*>(br->rho);
+  cplx<T>* W = static_cast<cplx<T>*>(br->W);
+  const bool sasha = g.method == 1;
+  const double dz = g.lz / nz;
+  cplx<T>* mytile = tile + sub * SLOTS;
+  load_twiddles<T, NY, NT>(tw, twy, tid);
+
+  PlanePhase pp[POS];
+#pragma unroll
+  for (int i = 0; i < POS; ++i) {
+    const int q = tid + i * NT;
+    pp[i].init(q < QN ? q / NB : 0, j, B, br->fy);
+  }
+
+  cplx<T> acc[A][POS][2];
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int a0 = 0; a0 < A; a0 += PG) {
+    // PG thread groups transform planes a0 .. a0+PG-1 (x = j + B a) into their LDS tiles
+    const int x = j + B * (a0 + sub);
+    const T* src = rho + (size_t)x * NY * nz + z0;
+    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true>(
+        mytile, tw, stid,
+        [&](int e, int c) {
+          cplx<T> v = mk<T>(T(0), T(0));
+          if (2 * c < zn) {
+            v = *reinterpret_cast<const cplx<T>*>(src + (size_t)e * nz + 2 * c);
+            if (sasha) {
+              const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
+              s0 += (double)v.x + (double)v.y;
+              s1 += za * (double)v.x + (za + dz) * (double)v.y;
+            }
+          }
+          return v;
+        },
+        [&](int e, int c, cplx<T> v) { mytile[L::at(e, c)] = v; });
+    __syncthreads();
+    // every thread collects its positions of all PG planes: separate, remap, keep in registers
+#pragma unroll
+    for (int sp = 0; sp < PG; ++sp) {
+      const cplx<T>* tl = tile + sp * SLOTS;
+#pragma unroll
+      for (int i = 0; i < POS; ++i) {
+        const int q = tid + i * NT;
+        acc[a0 + sp][i][0] = acc[a0 + sp][i][1] = mk<T>(T(0), T(0));
+        if (q < QN) {
+          const int ky = q / NB, c = q - ky * NB;
+          const cplx<T> c1 = tl[L::at(ky, c)];
+          const cplx<T> c2 = tl[L::at((NY - ky) % NY, c)];
+          const cplx<T> p = mk<T>((T)pp[i].pr, (T)pp[i].pi);
+          acc[a0 + sp][i][0] = cmul<T>(mk<T>(T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)), p);
+          acc[a0 + sp][i][1] = cmul<T>(mk<T>(T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)), p);
+        }
+        pp[i].step();
+      }
+    }
+    __syncthreads();  // the tiles are reused by the next planes
+  }
+
+  if (sasha) {
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_down(s0, o);
+      s1 += __shfl_down(s1, o);
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = s0;
+      red[1][tid >> 6] = s1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sa = 0.0, sb = 0.0;
+      for (int i = 0; i < NT / 64; ++i) {
+        sa += red[0][i];
+        sb += red[1][i];
+      }
+      br->partials[2 * t] = sa;
+      br->partials[2 * t + 1] = sb;
+    }
+  }
+
+  // A-point DFT across planes, twiddle w_Nx^(j k1), store
+  const int nx = g.nx;
+#pragma unroll
+  for (int i = 0; i < POS; ++i) {
+    const int q = tid + i * NT;
+    if (q >= QN) continue;
+    const int ky = q / NB, c = q - ky * NB;
+    if (2 * c >= zn) continue;
+    cplx<T> va[A], vb[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      va[a] = acc[a][i][0];
+      vb[a] = acc[a][i][1];
+    }
+    Dft<A, -1, T>::run(va);
+    Dft<A, -1, T>::run(vb);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      const cplx<T> w = twx[(j * k1) % nx];
+      const cplx<T> ra = cmul<T>(va[k1], w), rb = cmul<T>(vb[k1], w);
+      cplx<T>* dst = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(dst) = make_float4(ra.x, ra.y, rb.x, rb.y);
+      } else {
+        dst[0] = ra;
+        dst[1] = rb;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pass C: inverse of pass A.  Load W[k1][my][j][z chunk] for all k1, conjugate twiddle,
+// A-point inverse DFT across k1 in registers, then per plane: reverse remap, Hermitian columns
+// in LDS, inverse y transform straight to phi (+ Phi_0 for SASHA).
+
+template <typename T, int NY, int A, int B, int V>
+__global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                 const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+  constexpr int ZC = fa_zc<T, V>();
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kFusedAC;
+  constexpr int PG = A < 4 ? A : 4;
+  constexpr int TNT = NT / PG;
+  constexpr int HY = NY / 2;
+  constexpr int QN = HY * NB;
+  constexpr int POS = (QN + NT - 1) / NT;
+  constexpr int SLOTS = lds_slots(NY * NB);
+  using L = Tile<NB, NB, 1, true>;
+  __shared__ cplx<T> tile[PG * SLOTS];
+  __shared__ cplx<T> tw[NY];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int sub = tid / TNT, stid = tid - sub * TNT;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int j = t / nzc;
+  const int z0 = (t - j * nzc) * ZC;
+  const int zn = min(ZC, nz - z0);
+  const cplx<T>* W = static_cast<const cplx<T>*>(br->W);
+  T* phi = static_cast<T*>(br->phi);
+  const int nx = g.nx;
+  cplx<T>* mytile = tile + sub * SLOTS;
+  load_twiddles<T, NY, NT>(tw, twy, tid);
+
+  cplx<T> acc[A][POS][2];
+  PlanePhase pp[POS];
+#pragma unroll
+  for (int i = 0; i < POS; ++i) {
+    const int q = tid + i * NT;
+    const int ky = q < QN ? q / NB : 0, c = q < QN ? q - ky * NB : 0;
+    pp[i].init(ky, j, B, br->fy);
+    cplx<T> va[A], vb[A];
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      va[k1] = vb[k1] = mk<T>(T(0), T(0));
+      if (q < QN && 2 * c < zn) {
+        const cplx<T>* src = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
+        cplx<T> a0, b0;
+        if constexpr (sizeof(T) == 4) {
+          const float4 v4 = *reinterpret_cast<const float4*>(src);
+          a0 = mk<T>(v4.x, v4.y);
+          b0 = mk<T>(v4.z, v4.w);
+        } else {
+          a0 = src[0];
+          b0 = src[1];
+        }
+        const cplx<T> w = twx[(j * k1) % nx];
+        va[k1] = cmulc<T>(a0, w);
+        vb[k1] = cmulc<T>(b0, w);
+      }
+    }
+    Dft<A, +1, T>::run(va);
+    Dft<A, +1, T>::run(vb);
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      acc[a][i][0] = va[a];
+      acc[a][i][1] = vb[a];
+    }
+  }
+
+  const bool sasha = g.method == 1;
+  double c2 = 0.0, c1 = 0.0;
+  if (sasha) {
+    c2 = br->coef->c2;
+    c1 = br->coef->c1;
+  }
+  const double dz = g.lz / nz;
+#pragma unroll
+  for (int a0 = 0; a0 < A; a0 += PG) {
+    // every thread writes its positions of planes a0 .. a0+PG-1 as Hermitian columns
+#pragma unroll
+    for (int sp = 0; sp < PG; ++sp) {
+      cplx<T>* tl = tile + sp * SLOTS;
+      const auto& cur = acc[a0 + sp];
+      for (int c = tid; c < NB; c += NT) tl[L::at(HY, c)] = mk<T>(T(0), T(0));  // y Nyquist
+#pragma unroll
+      for (int i = 0; i < POS; ++i) {
+        const int q = tid + i * NT;
+        if (q < QN) {
+          const int ky = q / NB, c = q - ky * NB;
+          const cplx<T> p = mk<T>((T)pp[i].pr, (T)pp[i].pi);  // exp(-i theta); conjugated here
+          const cplx<T> av = cmulc<T>(cur[i][0], p), bv = cmulc<T>(cur[i][1], p);
+          if (ky == 0) {
+            tl[L::at(0, c)] = mk<T>(av.x, bv.x);
+          } else {
+            tl[L::at(ky, c)] = mk<T>(av.x - bv.y, av.y + bv.x);
+            tl[L::at(NY - ky, c)] = mk<T>(av.x + bv.y, bv.x - av.y);
+          }
+        }
+        pp[i].step();
+      }
+    }
+    __syncthreads();
+    // PG thread groups run the inverse y transforms of their planes straight to phi
+    const int x = j + B * (a0 + sub);
+    T* dst = phi + (size_t)x * NY * nz + z0;
+    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
+        mytile, tw, stid, [&](int e, int c) { return mytile[L::at(e, c)]; },
+        [&](int e, int c, cplx<T> v) {
+          if (2 * c < zn) {
+            if (sasha) {
+              const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
+              const double zb = za + dz;
+              v.x = (T)((double)v.x + (c2 * za + c1) * za);
+              v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
+            }
+            *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
+          }
+        });
+    __syncthreads();  // the tiles are rebuilt for the next planes
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pass B: one block per (k1, my).  B-point DFT across the j pencils in registers (each thread
+// owns z positions), pencils parked in LDS, then groups of G pencils go through the padded z
+// transform / Green multiply / inverse (Kx = k1 + A k2), then the inverse B-point DFT.
+
+template <typename T, int M, int B, int Q>
+__global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                const cplx<T>* __restrict__ twm, const double2* __restrict__ twm64,
+                                                int A) {
+  constexpr int NT = kFusedB;
+  constexpr int NZ = M / Q;
+  constexpr int G = fb_group<T, M, B>();
+  constexpr bool kF32 = std::is_same<T, float>::value;
+  using LT = Tile<B, 1, NZ, false>;  // parked pencils: element z of pencil k2
+  using LX = Tile<G, 1, M, false>;   // z-transform exchange tile
+  __shared__ cplx<T> tile[lds_slots(B * NZ)];
+  __shared__ cplx<T> xbuf[lds_slots(G * M)];
+  __shared__ cplx<T> tw[M];
+  __shared__ T pa0[G], pe[G], pik[G], pk2[G];
+  __shared__ int pzero[G];
+  __shared__ double2 d0[kF32 ? NZ : 1];  // float plans: the k = 0 pencil input in double
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int hy = g.ny / 2;
+  const int k1 = t / hy, my = t - k1 * hy;
+  const bool sasha = g.method == 1;
+  const double scale = br->scale;
+  cplx<T>* base = static_cast<cplx<T>*>(br->W) + (size_t)t * B * NZ;
+  const T* zs2 = static_cast<const T*>(br->zt[0]);
+  const T* zks = static_cast<const T*>(br->zt[1]);
+  const T* zkz2 = static_cast<const T*>(br->zt[2]);
+  const bool own0 = kF32 && t == 0;  // this block holds Kx = Ky = 0 (pencil k2 = 0)
+  load_twiddles<T, M, NT>(tw, twm, tid);
+
+  // B-point DFT across j for each z
+  for (int z = tid; z < NZ; z += NT) {
+    cplx<T> v[B];
+#pragma unroll
+    for (int jj = 0; jj < B; ++jj) v[jj] = base[(size_t)jj * NZ + z];
+    if (own0) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        sx += (double)v[jj].x;
+        sy += (double)v[jj].y;
+      }
+      d0[kF32 ? z : 0] = make_double2(sx, sy);
+    }
+    Dft<B, -1, T>::run(v);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) tile[LT::at(z, k2)] = v[k2];
+  }
+
+  // SASHA: <rho> and the centre of mass from the pass-A partial sums (fixed order)
+  if (sasha && t == 0) {
+    __shared__ double red[2][NT];
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < br->npartials; i += NT) {
+      a += br->partials[2 * i];
+      b += br->partials[2 * i + 1];
+    }
+    red[0][tid] = a;
+    red[1][tid] = b;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        red[0][tid] += red[0][tid + o];
+        red[1][tid] += red[1][tid + o];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double s0 = red[0][0], s1 = red[1][0];
+      SashaCoef c;
+      c.c2 = 0.0;
+      c.c1 = 0.0;
+      if (s0 != 0.0) {
+        const double mean = s0 / ((double)g.nx * g.ny * g.m);
+        c.c2 = 0.5 * br->fourpiG * mean;
+        c.c1 = -br->fourpiG * mean * (s1 / s0);
+      }
+      *br->coef = c;
+    }
+  }
+  __syncthreads();
+
+  // float plans: the k = 0 pencil in double, exchanged through xbuf, result parked in the tile
+  if constexpr (kF32) {
+    if (t == 0) {
+      using L1 = Tile<1, 1, M, false>;
+      double2* dbuf = reinterpret_cast<double2*>(xbuf);
+      const double* z64s2 = br->zt64[0];
+      const double* z64ks = br->zt64[1];
+      const double* z64kz2 = br->zt64[2];
+      fft_fwd_op_inv<double, M, L1, NT, 0, Q>(
+          dbuf, twm64, tid, [&](int e, int) { return e < NZ ? d0[e] : make_double2(0.0, 0.0); },
+          [&](int mz, int, double2& v) {
+            double gk;
+            if (sasha)
+              gk = mz == 0 ? 0.0 : -1.0 / z64kz2[mz];
+            else
+              gk = mz == 0 ? 0.5 * g.L * g.L : (g.L * z64ks[mz] - z64s2[mz]) / z64kz2[mz];
+            gk *= scale;
+            v.x *= gk;
+            v.y *= gk;
+          },
+          [&](int e, int, double2 v) {
+            if (e < NZ) tile[LT::at(e, 0)] = make_float2((float)v.x, (float)v.y);
+          });
+      __syncthreads();
+    }
+  }
+
+  const int nx = g.nx;
+  const double two_pi = 6.283185307179586476925286766559;
+  const double Ky = (two_pi / g.ly) * my;
+  const T L_ = (T)g.L;
+  const T sc = (T)scale;
+#pragma unroll 1
+  for (int g0 = 0; g0 < B; g0 += G) {
+    if (tid < G) {
+      const int k2 = g0 + tid;
+      const int mx = k1 + A * k2;
+      const int sx = mx < nx / 2 ? mx : mx - nx;
+      const double kx = (two_pi / g.lx) * sx + br->s * Ky;
+      const double kk2 = kx * kx + Ky * Ky;
+      const double k = sqrt(kk2);
+      const int zero = (mx == 0 && my == 0);
+      pzero[tid] = zero;
+      pk2[tid] = (T)kk2;
+      if (!zero && !sasha) {
+        pa0[tid] = (T)(-expm1(-k * g.L) * scale);
+        pe[tid] = (T)(exp(-k * g.L) * scale);
+        pik[tid] = (T)(1.0 / k);
+      } else {
+        pa0[tid] = T(0);
+        pe[tid] = T(0);
+        pik[tid] = T(0);
+      }
+    }
+    __syncthreads();
+    fft_fwd_op_inv<T, M, LX, NT, 0, Q>(
+        xbuf, tw, tid,
+        [&](int e, int p) {
+          return (e < NZ && !(own0 && g0 + p == 0)) ? tile[LT::at(e, g0 + p)] : mk<T>(T(0), T(0));
+        },
+        [&](int mz, int p, cplx<T>& v) {
+          const T s2 = zs2[mz], ks = zks[mz], kz2 = zkz2[mz];
+          T gk;
+          if (sasha) {
+            gk = (pzero[p] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[p] + kz2);
+          } else if (!pzero[p]) {
+            gk = -(pa0[p] + pe[p] * (s2 + pik[p] * ks)) * fast_rcp(pk2[p] + kz2);
+          } else {
+            gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
+          }
+          v.x *= gk;
+          v.y *= gk;
+        },
+        [&](int e, int p, cplx<T> v) {
+          if (e < NZ && !(own0 && g0 + p == 0)) tile[LT::at(e, g0 + p)] = v;
+        });
+    __syncthreads();  // pencil results parked; scalars and xbuf reused by the next group
+  }
+
+  // inverse B-point DFT across k2, store
+  for (int z = tid; z < NZ; z += NT) {
+    cplx<T> v[B];
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) v[k2] = tile[LT::at(z, k2)];
+    Dft<B, +1, T>::run(v);
+#pragma unroll
+    for (int jj = 0; jj < B; ++jj) base[(size_t)jj * NZ + z] = v[jj];
+  }
+}
+
+template <typename T>
+hipError_t launch_fused_impl(int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+                             const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
+template <> hipError_t launch_fused_impl<float>(int, int, int, int, int, GroupArgs, int, const BoxRec*, const void*,
+                                                const void*, hipStream_t);
+template <> hipError_t launch_fused_impl<double>(int, int, int, int, int, GroupArgs, int, const BoxRec*, const void*,
+                                                 const void*, hipStream_t);
+
+template <typename T> int fused_ac_tiles_t(const BoxGeom& g, int variant) {
+  const int zc = variant ? fa_zc<T, 1>() : fa_zc<T, 0>();
+  return kFusedB16 * ((g.nz + zc - 1) / zc);
+}
+
+}  // namespace sbp

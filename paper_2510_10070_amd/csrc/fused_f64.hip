@@ -1,0 +1,43 @@
+// Fused three-pass schedule instantiated for double.
+#include "fused.hpp"
+
+namespace sbp {
+
+// kind: 0 = pass A (len = Ny), 1 = pass B (len = M, q = padding), 2 = pass C (len = Ny);
+// a = A = Nx/16.  tw: y twiddles (A, C) or z twiddles (B); tw2: x twiddles (A, C) or the
+// double z twiddles (B).
+template <>
+hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+                                 const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st) {
+  using T = double;
+  constexpr int B = kFusedB16;
+  const dim3 grid(blocks);
+  const cplx<T>* t1 = static_cast<const cplx<T>*>(tw);
+  (void)variant;
+  if (kind == 1) {
+    const double2* t64 = static_cast<const double2*>(tw2);
+#define SBP_CASE(M_)                                                                                           \
+    if (len == M_) {                                                                                           \
+      if (q == 4) hipLaunchKernelGGL((k_fb<T, M_, B, 4>), grid, dim3(kFusedB), 0, st, ga, recs, t1, t64, a);  \
+      else hipLaunchKernelGGL((k_fb<T, M_, B, 2>), grid, dim3(kFusedB), 0, st, ga, recs, t1, t64, a);        \
+      return hipGetLastError();                                                                                \
+    }
+    SBP_CASE(32) SBP_CASE(64) SBP_CASE(128) SBP_CASE(256) SBP_CASE(512)
+#undef SBP_CASE
+    return hipErrorInvalidValue;
+  }
+  const cplx<T>* t2 = static_cast<const cplx<T>*>(tw2);
+#define SBP_AC(NY_, A_)                                                                                     \
+  if (len == NY_ && a == A_) {                                                                               \
+    if (kind == 0) hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2); \
+    else hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);          \
+    return hipGetLastError();                                                                               \
+  }
+#define SBP_NY(NY_) SBP_AC(NY_, 1) SBP_AC(NY_, 2) SBP_AC(NY_, 4) SBP_AC(NY_, 8) SBP_AC(NY_, 16)
+  SBP_NY(16) SBP_NY(32) SBP_NY(64) SBP_NY(128) SBP_NY(256) SBP_NY(512)
+#undef SBP_NY
+#undef SBP_AC
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sbp

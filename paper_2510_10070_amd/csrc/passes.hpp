@@ -1,0 +1,507 @@
+// Streaming passes of the solve, written once for float and double and for several tile
+// shapes ("variants", chosen per plan, optionally by the autotuner).  Each launch serves a
+// group of boxes that share a kernel shape: block b of the launch finds its box by a search
+// over the group's block offsets, so many boxes of uneven size run in a few launches.
+//
+//   y forward  (a1 + a7): rho -> half spectrum W[x][my][z] (my < Ny/2), remap phase applied
+//   x          (a1 / a6): complex length-Nx transforms of W in place
+//   z          (a2 - a5): zero padding, z transform, Green multiply, inverse, extraction
+//   y inverse  (a6):      W -> phi, reverse remap, SASHA Phi_0
+#pragma once
+
+#include <type_traits>
+
+#include "fft_device.hpp"
+#include "sbp_internal.hpp"
+
+namespace sbp {
+
+constexpr int kPassThreads = 256;
+
+// ------------------------------------------------------------------------------------------
+// tile shapes per (precision, transform length, variant)
+
+// y: real z cells per tile (even); variant 1 = 128-byte rows, variant 0 = half of that
+template <typename T, int N, int V> constexpr int y_zc() {
+  constexpr int big = sizeof(T) == 4 ? (N <= 512 ? 32 : 16) : (N <= 512 ? 16 : 8);
+  return V ? big : big / 2;
+}
+// x: complex z cells per tile
+template <typename T, int N, int V> constexpr int x_zc() {
+  constexpr int big = sizeof(T) == 4 ? (N <= 512 ? 16 : 8) : (N <= 512 ? 8 : 4);
+  return V ? big : big / 2;
+}
+// z: pencils per tile (variant 1 targets a 32 KiB padded tile, variant 0 half of that)
+template <typename T, int M, int V> constexpr int z_pp() {
+  constexpr int pp = 32768 / (M * 2 * (int)sizeof(T));
+  constexpr int big = pp < 1 ? 1 : (pp > 32 ? 32 : pp);
+  return V ? big : (big > 1 ? big / 2 : 1);
+}
+
+// ------------------------------------------------------------------------------------------
+// launch groups
+
+__device__ __forceinline__ int find_box(const int* __restrict__ starts, int n, int blk) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (starts[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// locate this block's box and its tile index within the box (XCD-aware order over the launch)
+__device__ __forceinline__ const BoxRec* group_box(const GroupArgs& ga, const BoxRec* __restrict__ recs, int& tile) {
+  const int total = ga.starts[ga.n];
+  const int b = xcd_tile(blockIdx.x, total);
+  const int i = find_box(ga.starts, ga.n, b);
+  tile = b - ga.starts[i];
+  return recs + ga.box_ids[i];
+}
+
+// remap phase exp(-i 2 pi c) for c = my*(2x+1)*fy cycles, evaluated in double
+__device__ __forceinline__ void remap_phase(int my, int x, double fy, double& cs, double& sn) {
+  const double c = static_cast<double>(my * (2 * x + 1)) * fy;
+  const double r = c - floor(c);
+  double sv, cv;
+  sincospi(2.0 * r, &sv, &cv);
+  cs = cv;
+  sn = -sv;
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+// ------------------------------------------------------------------------------------------
+// y forward: one block per (x plane, chunk of ZC consecutive z cells).  Consecutive z pairs
+// (z, z+1) are packed as one complex column, so one complex length-Ny FFT transforms two real
+// columns; the halves are separated, multiplied by exp(-i Ky s x_i) (shearing frame, Sect. 2.1)
+// and stored for my < Ny/2 (the Nyquist row is dropped).  SASHA: double partial sums.
+
+template <typename T, int NY, int V, bool REMAP>
+__global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                       const cplx<T>* __restrict__ twg) {
+  constexpr int ZC = y_zc<T, NY, V>();
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kPassThreads;
+  using L = Tile<NB, NB, 1, true>;
+  __shared__ cplx<T> tile[lds_slots(NY * NB)];
+  __shared__ cplx<T> tw[NY];
+  __shared__ cplx<T> ph[NY / 2];
+  __shared__ double red[2][NT / 64];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int x = t / nzc;
+  const int z0 = (t - x * nzc) * ZC;
+  const int hy = NY / 2;
+  const T* rho = static_cast<const T*>(br->rho);
+  cplx<T>* W = static_cast<cplx<T>*>(br->W);
+  double* partials = REMAP ? br->partials : nullptr;
+
+  load_twiddles<T, NY, NT>(tw, twg, tid);
+  if (REMAP) {
+    const double fy = br->fy;
+    for (int my = tid; my < hy; my += NT) {
+      double cs, sn;
+      remap_phase(my, x, fy, cs, sn);
+      ph[my] = mk<T>((T)cs, (T)sn);
+    }
+  }
+  if (partials) {
+    double s0 = 0.0, s1 = 0.0;
+    const double dz = g.lz / nz;
+    for (int w = tid; w < NY * NB; w += NT) {
+      const int c = w % NB, y = w / NB;
+      const int z = z0 + 2 * c;
+      if (z < nz) {
+        const cplx<T> v = *reinterpret_cast<const cplx<T>*>(rho + ((size_t)x * NY + y) * nz + z);
+        const double za = -0.5 * g.lz + (z + 0.5) * dz;
+        s0 += (double)v.x + (double)v.y;
+        s1 += za * (double)v.x + (za + dz) * (double)v.y;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_down(s0, o);
+      s1 += __shfl_down(s1, o);
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = s0;
+      red[1][tid >> 6] = s1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int i = 0; i < NT / 64; ++i) {
+        a += red[0][i];
+        b += red[1][i];
+      }
+      partials[2 * t] = a;
+      partials[2 * t + 1] = b;
+    }
+  }
+
+  const T* src = rho + (size_t)x * NY * nz + z0;
+  const int zn = min(ZC, nz - z0);
+  fft_run<T, NY, typename Fwd<NY>::L, L, NT, -1, false, true>(
+      tile, tw, tid,
+      [&](int e, int c) {
+        return 2 * c < zn ? *reinterpret_cast<const cplx<T>*>(src + (size_t)e * nz + 2 * c) : mk<T>(T(0), T(0));
+      },
+      [&](int e, int c, cplx<T> v) { tile[L::at(e, c)] = v; });
+  __syncthreads();
+
+  for (int w = tid; w < hy * NB; w += NT) {
+    const int c = w % NB, ky = w / NB;
+    if (2 * c >= zn) continue;
+    const cplx<T> c1 = tile[L::at(ky, c)];
+    const cplx<T> c2 = tile[L::at((NY - ky) % NY, c)];
+    cplx<T> a = mk<T>(T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y));
+    cplx<T> b = mk<T>(T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x));
+    if (REMAP) {
+      const cplx<T> p = ph[ky];
+      a = cmul<T>(a, p);
+      b = cmul<T>(b, p);
+    }
+    cplx<T>* dst = W + ((size_t)x * hy + ky) * nz + z0 + 2 * c;
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, b.x, b.y);
+    } else {
+      dst[0] = a;
+      dst[1] = b;
+    }
+  }
+}
+
+// y inverse: half spectra times exp(+i Ky s x_i), rebuilt into two Hermitian columns packed
+// as one complex signal, one inverse FFT, real/imaginary parts written as z and z+1, plus
+// Phi_0(z) for SASHA.
+template <typename T, int NY, int V, bool REMAP>
+__global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                       const cplx<T>* __restrict__ twg) {
+  constexpr int ZC = y_zc<T, NY, V>();
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kPassThreads;
+  using L = Tile<NB, NB, 1, true>;
+  __shared__ cplx<T> tile[lds_slots(NY * NB)];
+  __shared__ cplx<T> tw[NY];
+  __shared__ cplx<T> ph[NY / 2];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int x = t / nzc;
+  const int z0 = (t - x * nzc) * ZC;
+  const int hy = NY / 2;
+  const cplx<T>* W = static_cast<const cplx<T>*>(br->W);
+  T* phi = static_cast<T*>(br->phi);
+  const int zn = min(ZC, nz - z0);
+
+  load_twiddles<T, NY, NT>(tw, twg, tid);
+  if (REMAP) {
+    const double fy = br->fy;
+    for (int my = tid; my < hy; my += NT) {
+      double cs, sn;
+      remap_phase(my, x, fy, cs, sn);
+      ph[my] = mk<T>((T)cs, (T)sn);  // exp(-i theta); used conjugated below
+    }
+  }
+  for (int c = tid; c < NB; c += NT) tile[L::at(hy, c)] = mk<T>(T(0), T(0));  // y Nyquist
+  __syncthreads();
+
+  for (int w = tid; w < hy * NB; w += NT) {
+    const int c = w % NB, ky = w / NB;
+    cplx<T> a = mk<T>(T(0), T(0)), b = a;
+    if (2 * c < zn) {
+      const cplx<T>* src = W + ((size_t)x * hy + ky) * nz + z0 + 2 * c;
+      if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(src);
+        a = mk<T>(q.x, q.y);
+        b = mk<T>(q.z, q.w);
+      } else {
+        a = src[0];
+        b = src[1];
+      }
+      if (REMAP) {
+        a = cmulc<T>(a, ph[ky]);
+        b = cmulc<T>(b, ph[ky]);
+      }
+    }
+    if (ky == 0) {
+      tile[L::at(0, c)] = mk<T>(a.x, b.x);  // the DC terms of real columns are real
+    } else {
+      tile[L::at(ky, c)] = mk<T>(a.x - b.y, a.y + b.x);       // A + iB
+      tile[L::at(NY - ky, c)] = mk<T>(a.x + b.y, b.x - a.y);  // conj(A) + i conj(B)
+    }
+  }
+  __syncthreads();
+
+  const bool sasha = REMAP && g.method == 1;
+  double c2 = 0.0, c1 = 0.0;
+  if (sasha) {
+    c2 = br->coef->c2;
+    c1 = br->coef->c1;
+  }
+  const double dz = g.lz / nz;
+  T* dst = phi + (size_t)x * NY * nz + z0;
+  fft_run<T, NY, typename Fwd<NY>::L, L, NT, +1, true, false>(
+      tile, tw, tid, [&](int e, int c) { return tile[L::at(e, c)]; },
+      [&](int e, int c, cplx<T> v) {
+        if (2 * c < zn) {
+          if (sasha) {
+            const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
+            const double zb = za + dz;
+            v.x = (T)((double)v.x + (c2 * za + c1) * za);
+            v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
+          }
+          *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
+        }
+      });
+}
+
+// ------------------------------------------------------------------------------------------
+// x: one block per (my, chunk of ZC consecutive z cells); rows of ZC contiguous complex values.
+
+template <typename T, int NX, int V, int D>
+__global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                    const cplx<T>* __restrict__ twg) {
+  constexpr int ZC = x_zc<T, NX, V>();
+  constexpr int NT = kPassThreads;
+  using L = Tile<ZC, ZC, 1, true>;
+  __shared__ cplx<T> buf[lds_slots(NX * ZC)];
+  __shared__ cplx<T> tw[NX];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int hy = g.ny / 2;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int my = t / nzc;
+  const int z0 = (t - my * nzc) * ZC;
+  const int zn = min(ZC, nz - z0);
+  const size_t row = (size_t)hy * nz;
+  cplx<T>* base = static_cast<cplx<T>*>(br->W) + (size_t)my * nz + z0;
+  load_twiddles<T, NX, NT>(tw, twg, tid);
+  fft_run<T, NX, typename Fwd<NX>::L, L, NT, D, false, false>(
+      buf, tw, tid, [&](int e, int c) { return c < zn ? base[e * row + c] : mk<T>(T(0), T(0)); },
+      [&](int e, int c, cplx<T> v) {
+        if (c < zn) base[e * row + c] = v;
+      });
+}
+
+// ------------------------------------------------------------------------------------------
+// z: one block per PP consecutive (Kx, Ky) pencils (contiguous in W).  Each pencil is padded
+// to M = Q*Nz (Hockney; never stored), transformed, multiplied by the Green's function at
+// k = |(Kx + s Ky, Ky)| (Sect. 2.1) times 4 pi G/(Nx Ny M), transformed back; its first Nz
+// values are stored in place.  The forward output feeds the inverse in registers; the zero
+// half of the input and the discarded half of the output are dropped at compile time.
+//
+// Green's function (Sect. 2.3, App. A), L = alpha Lz, E = exp(-kL):
+//   VGF, k > 0:  -((1 - E) + E (1 - cos(kz L)) + E (kz/k) sin(kz L)) / (k^2 + kz^2)
+//                (the printed form regrouped; 1 - E = -expm1(-kL) and 1 - cos = 2 sin^2(kz L/2)
+//                come from accurate tables, so nothing cancels);
+//   VGF, k = 0:  (kz L sin(kz L) + cos(kz L) - 1) / kz^2, L^2/2 at kz = 0;
+//   SASHA:       -1/(k^2 + kz^2), 0 for the zero mode (mean subtraction, Sect. 2.2).
+// Per-pencil scalars are evaluated in double and rounded once; float plans run the k = 0
+// pencil (the horizontal mean, which carries most of the potential) entirely in double.
+
+template <typename T, int M, int V, int Q>
+__global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                    const cplx<T>* __restrict__ twg, const double2* __restrict__ tw64) {
+  constexpr int PP = z_pp<T, M, V>();
+  constexpr int NT = kPassThreads;
+  constexpr bool kF32 = std::is_same<T, float>::value;
+  using L = Tile<PP, 1, M, false>;
+  __shared__ cplx<T> buf[lds_slots(PP * M)];
+  __shared__ cplx<T> tw[M];
+  __shared__ T pa0[PP], pe[PP], pik[PP], pk2[PP];
+  __shared__ int pzero[PP];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int hy = g.ny / 2;
+  const int np = g.nx * hy;
+  const int p0 = t * PP;
+  const int nz = g.nz;
+  const int nvalid = min(PP, np - p0);
+  const bool sasha = g.method == 1;
+  const double scale = br->scale;
+  cplx<T>* W = static_cast<cplx<T>*>(br->W);
+  cplx<T>* base = W + (size_t)p0 * nz;
+  const T* zs2 = static_cast<const T*>(br->zt[0]);
+  const T* zks = static_cast<const T*>(br->zt[1]);
+  const T* zkz2 = static_cast<const T*>(br->zt[2]);
+
+  load_twiddles<T, M, NT>(tw, twg, tid);
+  if (tid < PP) {
+    const int q = p0 + tid;
+    const int mx = q / hy, my = q - mx * hy;
+    const int sx = mx < g.nx / 2 ? mx : mx - g.nx;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double Ky = (two_pi / g.ly) * my;
+    const double kx = (two_pi / g.lx) * sx + br->s * Ky;
+    const double k2 = kx * kx + Ky * Ky;
+    const double k = sqrt(k2);
+    const int zero = (mx == 0 && my == 0);
+    pzero[tid] = zero;
+    pk2[tid] = (T)k2;
+    if (!zero && !sasha) {
+      pa0[tid] = (T)(-expm1(-k * g.L) * scale);
+      pe[tid] = (T)(exp(-k * g.L) * scale);
+      pik[tid] = (T)(1.0 / k);
+    } else {
+      pa0[tid] = T(0);
+      pe[tid] = T(0);
+      pik[tid] = T(0);
+    }
+  }
+
+  // SASHA: <rho> and the centre of mass from the y-pass partial sums (fixed order)
+  if (sasha && t == 0) {
+    __shared__ double red[2][NT];
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < br->npartials; i += NT) {
+      a += br->partials[2 * i];
+      b += br->partials[2 * i + 1];
+    }
+    red[0][tid] = a;
+    red[1][tid] = b;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        red[0][tid] += red[0][tid + o];
+        red[1][tid] += red[1][tid + o];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double s0 = red[0][0], s1 = red[1][0];
+      SashaCoef c;
+      c.c2 = 0.0;
+      c.c1 = 0.0;
+      if (s0 != 0.0) {
+        const double mean = s0 / ((double)g.nx * g.ny * g.m);
+        c.c2 = 0.5 * br->fourpiG * mean;
+        c.c1 = -br->fourpiG * mean * (s1 / s0);
+      }
+      *br->coef = c;
+    }
+  }
+
+  // float plans: the k = 0 pencil (pencil 0 of tile 0) in double, using the exchange tile
+  const bool own0 = kF32 && t == 0;
+  if constexpr (kF32) {
+    if (t == 0) {
+      using L1 = Tile<1, 1, M, false>;
+      double2* dbuf = reinterpret_cast<double2*>(buf);
+      float2* w0 = reinterpret_cast<float2*>(W);
+      const double* z64s2 = br->zt64[0];
+      const double* z64ks = br->zt64[1];
+      const double* z64kz2 = br->zt64[2];
+      fft_fwd_op_inv<double, M, L1, NT, 0, Q>(
+          dbuf, tw64, tid,
+          [&](int e, int) { return e < nz ? make_double2((double)w0[e].x, (double)w0[e].y) : make_double2(0.0, 0.0); },
+          [&](int mz, int, double2& v) {
+            double gk;
+            if (sasha)
+              gk = mz == 0 ? 0.0 : -1.0 / z64kz2[mz];
+            else
+              gk = mz == 0 ? 0.5 * g.L * g.L : (g.L * z64ks[mz] - z64s2[mz]) / z64kz2[mz];
+            gk *= scale;
+            v.x *= gk;
+            v.y *= gk;
+          },
+          [&](int e, int, double2 v) {
+            if (e < nz) w0[e] = make_float2((float)v.x, (float)v.y);
+          });
+    }
+  }
+  __syncthreads();
+
+  const T L_ = (T)g.L;
+  const T sc = (T)scale;
+  fft_fwd_op_inv<T, M, L, NT, 0, Q>(
+      buf, tw, tid,
+      [&](int e, int p) {
+        return (e < nz && p < nvalid && !(own0 && p == 0)) ? base[(size_t)p * nz + e] : mk<T>(T(0), T(0));
+      },
+      [&](int mz, int p, cplx<T>& v) {
+        const T s2 = zs2[mz], ks = zks[mz], kz2 = zkz2[mz];
+        T gk;
+        if (sasha) {
+          gk = (pzero[p] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[p] + kz2);
+        } else if (!pzero[p]) {
+          gk = -(pa0[p] + pe[p] * (s2 + pik[p] * ks)) * fast_rcp(pk2[p] + kz2);
+        } else {
+          gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
+        }
+        v.x *= gk;
+        v.y *= gk;
+      },
+      [&](int e, int p, cplx<T> v) {
+        if (e < nz && p < nvalid && !(own0 && p == 0)) base[(size_t)p * nz + e] = v;
+      });
+}
+
+// ------------------------------------------------------------------------------------------
+// host-side dispatch helpers (instantiated per precision in the pass translation units)
+
+template <typename T> int y_tiles_t(const BoxGeom& g, int variant) {
+  int zc = 0;
+#define SBP_CASE(N_) \
+  if (g.ny == N_) zc = variant ? y_zc<T, N_, 1>() : y_zc<T, N_, 0>();
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  return zc ? g.nx * ((g.nz + zc - 1) / zc) : 0;
+}
+template <typename T> int x_tiles_t(const BoxGeom& g, int variant) {
+  int zc = 0;
+#define SBP_CASE(N_) \
+  if (g.nx == N_) zc = variant ? x_zc<T, N_, 1>() : x_zc<T, N_, 0>();
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  return zc ? (g.ny / 2) * ((g.nz + zc - 1) / zc) : 0;
+}
+template <typename T> int z_tiles_t(const BoxGeom& g, int variant) {
+  int pp = 0;
+#define SBP_CASE(N_) \
+  if (g.m == N_) pp = variant ? z_pp<T, N_, 1>() : z_pp<T, N_, 0>();
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  const int np = g.nx * (g.ny / 2);
+  return pp ? (np + pp - 1) / pp : 0;
+}
+
+// per-precision launchers, specialised in the pass translation units
+template <typename T>
+hipError_t launch_y_impl(bool forward, bool remap, int ny, int variant, GroupArgs ga, int blocks, const BoxRec* recs,
+                         const void* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_x_impl(int dir, int nx, int variant, GroupArgs ga, int blocks, const BoxRec* recs, const void* tw,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_z_impl(int m, int variant, int q, GroupArgs ga, int blocks, const BoxRec* recs, const void* tw,
+                         const void* tw64, hipStream_t st);
+template <> hipError_t launch_y_impl<float>(bool, bool, int, int, GroupArgs, int, const BoxRec*, const void*, hipStream_t);
+template <> hipError_t launch_y_impl<double>(bool, bool, int, int, GroupArgs, int, const BoxRec*, const void*, hipStream_t);
+template <> hipError_t launch_x_impl<float>(int, int, int, GroupArgs, int, const BoxRec*, const void*, hipStream_t);
+template <> hipError_t launch_x_impl<double>(int, int, int, GroupArgs, int, const BoxRec*, const void*, hipStream_t);
+template <> hipError_t launch_z_impl<float>(int, int, int, GroupArgs, int, const BoxRec*, const void*, const void*,
+                                            hipStream_t);
+template <> hipError_t launch_z_impl<double>(int, int, int, GroupArgs, int, const BoxRec*, const void*, const void*,
+                                             hipStream_t);
+
+}  // namespace sbp

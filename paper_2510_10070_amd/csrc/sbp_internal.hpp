@@ -8,7 +8,7 @@
 
 namespace sbp {
 
-// Static geometry of one box, passed to kernels by value.
+// Static geometry of one box.
 struct BoxGeom {
   int nx, ny, nz;  // physical cells; ny/2 stored y modes (Nyquist dropped)
   int m;           // padded z length P*nz
@@ -17,25 +17,36 @@ struct BoxGeom {
   double L;        // truncation length alpha*lz of the VGF kernel
 };
 
-// Per-solve scalars of one box, written to device memory before each solve.
-struct SolveScalars {
-  double s;      // Delta_y0/Lx: shear of the wave vector, kx = Kx + s Ky
-  double fy;     // Delta_y0/(2 Ly Nx): remap phase in cycles per unit of my*(2i+1)
-  double scale;  // 4 pi G/(Nx Ny M): Green's-function factor including DFT normalisation
-  double fourpiG;
-};
-
 // SASHA analytic part Phi_0(z) = c2 z^2 + c1 z, produced on the device from the reductions.
 struct SashaCoef {
   double c2, c1;
 };
 
-// Per-kz tables of the padded z grid (plan constants), in precision T:
-//   s2 = 1 - cos(kz L) = 2 sin^2(kz L/2),  ks = kz sin(kz L),  kz2 = kz^2.
-template <typename T> struct ZTables {
-  const T* s2;
-  const T* ks;
-  const T* kz2;
+// Everything a kernel needs about one box, in device memory.  The per-solve fields are
+// rewritten by one host-to-device copy per solve (also under graph replay).
+struct BoxRec {
+  BoxGeom g;
+  // per solve
+  const void* rho;
+  void* phi;
+  double s;        // Delta_y0/Lx: kx = Kx + s Ky
+  double fy;       // Delta_y0/(2 Ly Nx): remap phase in cycles per unit of my*(2i+1)
+  double scale;    // 4 pi G/(Nx Ny M)
+  double fourpiG;
+  // plan constants
+  void* W;         // half spectrum [nx][ny/2][nz] complex (plain path: padded [..][m])
+  double* partials;
+  int npartials;
+  SashaCoef* coef;
+  const void* zt[3];     // 1 - cos(kz L), kz sin(kz L), kz^2 in the plan precision
+  const double* zt64[3]; // the same in double
+};
+
+// A launch serves a group of boxes with the same kernel shape.
+struct GroupArgs {
+  const int* box_ids;  // boxes of the group (indices into the BoxRec array)
+  const int* starts;   // first block of each box; starts[n] = total blocks
+  int n;
 };
 
 // Supported transform lengths (x, y and padded z).
@@ -49,29 +60,33 @@ inline bool supported_len(int n) {
   return false;
 }
 
-// Launchers (defined in the pass translation units).  prec: 0 = double, 1 = float.
-hipError_t launch_yfwd(int prec, const BoxGeom& g, const void* rho, void* W, const void* tw_y,
-                       const SolveScalars* sp, double* partials, hipStream_t st);
-hipError_t launch_x(int prec, int dir, const BoxGeom& g, void* W, const void* tw_x, hipStream_t st);
-hipError_t launch_z(int prec, const BoxGeom& g, void* W, const void* tw_m, const void* tw_m64,
-                    const void* zt_s2, const void* zt_ks, const void* zt_kz2, const double* zt64_s2,
-                    const double* zt64_ks, const double* zt64_kz2, const SolveScalars* sp,
-                    const double* partials, int npartials, SashaCoef* coef, hipStream_t st);
-hipError_t launch_yinv(int prec, const BoxGeom& g, const void* W, void* phi, const void* tw_y,
-                       const SolveScalars* sp, const SashaCoef* coef, hipStream_t st);
+constexpr int kVariants = 2;  // tile variants per pass kernel
 
-// Number of SASHA partial-sum slots written by launch_yfwd for this box and precision.
-int yfwd_partials(int prec, const BoxGeom& g);
+// Tiles (= blocks) one box needs in each pass for a variant.  prec: 0 double, 1 float.
+int y_tiles(int prec, const BoxGeom& g, int variant);
+int x_tiles(int prec, const BoxGeom& g, int variant);
+int z_tiles(int prec, const BoxGeom& g, int variant);
 
-// Plain (unfused) FP64 path.
-hipError_t launch_y_plain(int dir, const BoxGeom& g, const double* in, double* out, const void* tw_y,
-                          hipStream_t st);
-hipError_t launch_zfft_plain(int dir, const BoxGeom& g, double* P, const void* tw_m, hipStream_t st);
+// Launchers; `blocks` is the total block count of the group (ga.starts[ga.n] on the host).
+hipError_t launch_y(int prec, bool forward, bool remap, int ny, int variant, GroupArgs ga, int blocks,
+                    const BoxRec* recs, const void* tw, hipStream_t st);
+hipError_t launch_x(int prec, int dir, int nx, int variant, GroupArgs ga, int blocks, const BoxRec* recs,
+                    const void* tw, hipStream_t st);
+hipError_t launch_z(int prec, int m, int variant, int q, GroupArgs ga, int blocks, const BoxRec* recs,
+                    const void* tw, const void* tw64, hipStream_t st);
+
+// Fused three-pass schedule (four-step x split Nx = A * 16).  kind: 0 pass A, 1 pass B, 2 pass C.
+bool fused_ok(const BoxGeom& g);
+int fused_ac_tiles(int prec, const BoxGeom& g, int variant);
+int fused_b_tiles(const BoxGeom& g);
+int fused_a(const BoxGeom& g);
+hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+                        const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
+
+// Plain (unfused) FP64 path for one box: rec0 views the half spectrum, rec_pad the padded one.
 constexpr int kPlainPartials = 1024;
-hipError_t launch_plain(const BoxGeom& g, const double* rho, double* phi, double* work_pad, double* work_half,
-                        const void* tw_x, const void* tw_y, const void* tw_m, const double* zt_s2,
-                        const double* zt_ks, const double* zt_kz2, const SolveScalars* sp,
-                        double* partials, SashaCoef* coef, hipStream_t st,
-                        void (*mark)(void*, const char*), void* mark_ctx);
+hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* d_rec0, const BoxRec* d_rec_pad, GroupArgs one,
+                        int y_var, int x_var, const void* tw_x, const void* tw_y, const void* tw_m,
+                        hipStream_t st, void (*mark)(void*, const char*), void* mark_ctx);
 
 }  // namespace sbp

@@ -1,6 +1,6 @@
-// Host side of the C ABI: descriptor validation, plan tables, workspace, launch sequence,
-// HIP-graph capture and kernel timing.  Every entry point catches all C++ exceptions and
-// reports through sbp_status plus a thread-local message.
+// Host side of the C ABI: descriptor validation, plan tables, workspace, launch groups, the
+// per-solve record copy, HIP-graph capture, kernel timing and the autotuner hooks.  Every entry
+// point catches all C++ exceptions and reports through sbp_status plus a thread-local message.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,15 +12,38 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
 #include "../../include/sbp.h"
 #include "sbp_internal.hpp"
+#include "tune.hpp"
 
 namespace {
 
 thread_local std::string g_last_error;
+
+#define HIP_TRY(expr)                                                                           \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return sbp::fail(SBP_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+const char* kPassName[8] = {"y_forward", "x_forward", "z_green", "x_inverse", "y_inverse",
+                            "fused_a", "fused_b", "fused_c"};
+
+}  // namespace
+
+namespace sbp {
 
 sbp_status fail(sbp_status st, const char* fmt, ...) {
   char buf[512];
@@ -32,57 +55,39 @@ sbp_status fail(sbp_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess) return fail(SBP_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace sbp
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
-
-struct ProfRec {
-  const char* name;
-  hipEvent_t a, b;
-};
-
-struct BoxPlan {
-  sbp::BoxGeom g;
-  size_t tw_x = 0, tw_y = 0, tw_m = 0, tw_m64 = 0;  // offsets into the table block
-  size_t zt[3] = {0, 0, 0}, zt64[3] = {0, 0, 0};
-  size_t ws_off = 0;     // complex half spectrum (fused) or padded spectrum (plain)
-  size_t ws2_off = 0;    // plain: unpadded half spectrum
-  size_t part_off = 0;   // SASHA partial sums (doubles) in the aux block
-  int npartials = 0;
-  size_t data_bytes = 0; // bytes of rho (= bytes of phi)
-};
-
-}  // namespace
+using sbp::BoxInfo;
+using sbp::fail;
+using sbp::Launch;
 
 struct sbp_plan_s {
   int device = 0;
   int prec = 0;  // 0 double, 1 float
   uint32_t flags = 0;
-  std::vector<BoxPlan> boxes;
+  std::vector<BoxInfo> boxes;
+  std::vector<Launch> launches;
+  std::vector<int> ints;  // host copy of the group int block
   char* d_tables = nullptr;
-  char* d_aux = nullptr;
-  sbp::SolveScalars* d_sp = nullptr;
+  char* d_aux = nullptr;  // records, coefficients, partial sums, group ints
+  sbp::BoxRec* d_recs = nullptr;
   sbp::SashaCoef* d_coef = nullptr;
   double* d_partials = nullptr;
+  int* d_ints = nullptr;
+  size_t nints_cap = 0;
+  std::vector<sbp::BoxRec> master;  // record templates (plan constants filled in)
   size_t ws_need = 0;
   char* ws = nullptr;
   bool ws_owned = false;
-  // pinned staging ring for per-solve scalars
-  sbp::SolveScalars* h_stage = nullptr;
+  // pinned staging ring for the per-solve records
+  sbp::BoxRec* h_stage = nullptr;
   int nslots = 0, slot = 0;
+  size_t nrec = 0;  // records per solve
   std::vector<hipEvent_t> slot_ev;
   std::vector<bool> slot_used;
   // graph mode
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<const void*> g_rho;
-  std::vector<void*> g_phi;
-  char* g_ws = nullptr;
   hipStream_t cap_stream = nullptr;  // capture happens here; replays go to the caller's stream
   // profiling
   bool prof = false;
@@ -91,13 +96,14 @@ struct sbp_plan_s {
   std::map<std::string, std::pair<long long, double>> totals;
   std::vector<std::string> names;  // stable storage for sbp_profile_read
   std::string describe;
+  std::string tune_source = "defaults";
 };
 
 namespace {
 
 size_t elem_size(int prec) { return prec ? sizeof(float) : sizeof(double); }
 
-sbp_status validate_box(const sbp_box& b, int i, int prec, uint32_t flags) {
+sbp_status validate_box(const sbp_box& b, int i, int prec) {
   if (!(b.nx > 0 && b.ny > 0 && b.nz > 0)) return fail(SBP_E_ARG, "box %d: non-positive cell count", i);
   if (!sbp::supported_len(b.nx)) return fail(SBP_E_SIZE, "box %d: nx=%d not a supported length", i, b.nx);
   if (!sbp::supported_len(b.ny)) return fail(SBP_E_SIZE, "box %d: ny=%d not a supported length", i, b.ny);
@@ -110,12 +116,12 @@ sbp_status validate_box(const sbp_box& b, int i, int prec, uint32_t flags) {
     return fail(SBP_E_ARG, "box %d: box lengths must be finite and > 0", i);
   if (!(std::isfinite(b.alpha)) || b.alpha < 0) return fail(SBP_E_ARG, "box %d: alpha must be >= 0", i);
   if (b.alpha != 0.0 && (b.alpha < 1.0 || b.alpha > 0.5 * pad))
-    return fail(SBP_E_ARG, "box %d: alpha=%g outside [1, pad/2]: periodic images of the truncated kernel "
-                           "would reach the box", i, b.alpha);
+    return fail(SBP_E_ARG,
+                "box %d: alpha=%g outside [1, pad/2]: periodic images of the truncated kernel would reach the box",
+                i, b.alpha);
   if (b.method != SBP_VGF && b.method != SBP_SASHA) return fail(SBP_E_ARG, "box %d: unknown method %d", i, b.method);
   const double n = (double)b.nx * b.ny * b.nz;
   if (n * elem_size(prec) > 64.0 * (1ull << 30)) return fail(SBP_E_SIZE, "box %d: grid too large", i);
-  (void)flags;
   return SBP_OK;
 }
 
@@ -223,38 +229,115 @@ struct Marker {
 
 void mark_cb(void* ctx, const char* name) { static_cast<Marker*>(ctx)->mark(name); }
 
-// launch one solve of every box; pointers already validated
-sbp_status enqueue(sbp_plan p, const void* const* rho, void* const* phi, hipStream_t st, Marker* mk) {
-  for (size_t b = 0; b < p->boxes.size(); ++b) {
-    const BoxPlan& bp = p->boxes[b];
-    const sbp::BoxGeom& g = bp.g;
-    const char* T = p->d_tables;
-    const sbp::SolveScalars* sp = p->d_sp + b;
-    sbp::SashaCoef* coef = p->d_coef + b;
-    double* part = g.method == SBP_SASHA ? p->d_partials + bp.part_off : nullptr;
-    if (p->flags & SBP_FLAG_PLAIN) {
-      HIP_TRY(sbp::launch_plain(g, (const double*)rho[b], (double*)phi[b], (double*)(p->ws + bp.ws_off),
-                                (double*)(p->ws + bp.ws2_off), T + bp.tw_x, T + bp.tw_y, T + bp.tw_m, (const double*)(T + bp.zt64[0]),
-                                (const double*)(T + bp.zt64[1]), (const double*)(T + bp.zt64[2]), sp,
-                                p->d_partials + bp.part_off, coef, st, mk ? mark_cb : nullptr, mk));
-      continue;
-    }
-    void* W = p->ws + bp.ws_off;
-    if (mk) mk->mark("y_forward");
-    HIP_TRY(sbp::launch_yfwd(p->prec, g, rho[b], W, T + bp.tw_y, sp, part, st));
-    if (mk) mk->mark("x_forward");
-    HIP_TRY(sbp::launch_x(p->prec, -1, g, W, T + bp.tw_x, st));
-    if (mk) mk->mark("z_green");
-    HIP_TRY(sbp::launch_z(p->prec, g, W, T + bp.tw_m, T + bp.tw_m64, T + bp.zt[0], T + bp.zt[1], T + bp.zt[2],
-                          (const double*)(T + bp.zt64[0]), (const double*)(T + bp.zt64[1]),
-                          (const double*)(T + bp.zt64[2]), sp, part, bp.npartials,
-                          g.method == SBP_SASHA ? coef : nullptr, st));
-    if (mk) mk->mark("x_inverse");
-    HIP_TRY(sbp::launch_x(p->prec, +1, g, W, T + bp.tw_x, st));
-    if (mk) mk->mark("y_inverse");
-    HIP_TRY(sbp::launch_yinv(p->prec, g, W, phi[b], T + bp.tw_y, sp, g.method == SBP_SASHA ? coef : nullptr, st));
-    if (mk) mk->mark(nullptr);
+int tiles_of(int prec, int kind, const sbp::BoxGeom& g, int variant) {
+  switch (kind) {
+    case sbp::kYFwd:
+    case sbp::kYInv: return sbp::y_tiles(prec, g, variant);
+    case sbp::kXFwd:
+    case sbp::kXInv: return sbp::x_tiles(prec, g, variant);
+    case sbp::kZ: return sbp::z_tiles(prec, g, variant);
+    case sbp::kFA:
+    case sbp::kFC: return sbp::fused_ac_tiles(prec, g, variant);
+    default: return sbp::fused_b_tiles(g);
   }
+}
+
+// transform length a launch of this kind is specialised on
+int kind_len(const BoxInfo& bi, int kind) {
+  switch (kind) {
+    case sbp::kYFwd:
+    case sbp::kYInv:
+    case sbp::kFA:
+    case sbp::kFC: return bi.g.ny;
+    case sbp::kZ:
+    case sbp::kFB: return bi.g.m;
+    default: return bi.g.nx;
+  }
+}
+
+bool kind_applies(const BoxInfo& bi, int kind) { return bi.fused ? kind >= sbp::kFA : kind < sbp::kFA; }
+
+// group boxes by kernel shape for each pass, in pass order
+void build_launches(sbp_plan p) {
+  p->launches.clear();
+  p->ints.clear();
+  const int nb = (int)p->boxes.size();
+  for (int phase = 0; phase < 5; ++phase)
+  for (int kind = 0; kind < sbp::kKinds; ++kind) {
+    if (sbp::kPhase[kind] != phase) continue;
+    // group key: transform length, tile variant, padding (z kinds), A (fused kinds)
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    for (int b = 0; b < nb; ++b) {
+      const BoxInfo& bi = p->boxes[b];
+      if (!kind_applies(bi, kind)) continue;
+      const int q = (kind == sbp::kZ || kind == sbp::kFB) ? bi.pad : 0;
+      const int a = kind >= sbp::kFA ? sbp::fused_a(bi.g) : 0;
+      groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a)].push_back(b);
+    }
+    for (auto& kv : groups) {
+      Launch l;
+      l.kind = kind;
+      std::tie(l.len, l.variant, l.q, l.a) = kv.first;
+      l.n = (int)kv.second.size();
+      l.ints_off = p->ints.size();
+      for (int b : kv.second) p->ints.push_back(b);
+      int acc = 0;
+      p->ints.push_back(0);
+      for (int b : kv.second) {
+        acc += tiles_of(p->prec, kind, p->boxes[b].g, l.variant);
+        p->ints.push_back(acc);
+      }
+      l.blocks = acc;
+      const BoxInfo& b0 = p->boxes[kv.second[0]];
+      switch (kind) {
+        case sbp::kYFwd:
+        case sbp::kYInv: l.tw = b0.tw_y; break;
+        case sbp::kZ: l.tw = b0.tw_m; l.tw64 = b0.tw_m64; break;
+        case sbp::kFA:
+        case sbp::kFC: l.tw = b0.tw_y; l.tw64 = b0.tw_x; break;
+        case sbp::kFB: l.tw = b0.tw_m; l.tw64 = b0.tw_m64; break;
+        default: l.tw = b0.tw_x;
+      }
+      p->launches.push_back(l);
+    }
+  }
+}
+
+hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
+  const char* T = p->d_tables;
+  sbp::GroupArgs ga{p->d_ints + l.ints_off, p->d_ints + l.ints_off + l.n, l.n};
+  switch (l.kind) {
+    case sbp::kYFwd:
+      return sbp::launch_y(p->prec, true, true, l.len, l.variant, ga, l.blocks, p->d_recs, T + l.tw, st);
+    case sbp::kYInv:
+      return sbp::launch_y(p->prec, false, true, l.len, l.variant, ga, l.blocks, p->d_recs, T + l.tw, st);
+    case sbp::kXFwd:
+    case sbp::kXInv:
+      return sbp::launch_x(p->prec, l.kind == sbp::kXFwd ? -1 : +1, l.len, l.variant, ga, l.blocks, p->d_recs,
+                           T + l.tw, st);
+    case sbp::kZ:
+      return sbp::launch_z(p->prec, l.len, l.variant, l.q, ga, l.blocks, p->d_recs, T + l.tw, T + l.tw64, st);
+    default:
+      return sbp::launch_fused(p->prec, l.kind - sbp::kFA, l.len, l.a, l.variant, l.q, ga, l.blocks, p->d_recs,
+                               T + l.tw, T + l.tw64, st);
+  }
+}
+
+// launch one solve (records already on the device)
+sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk) {
+  const char* T = p->d_tables;
+  if (p->flags & SBP_FLAG_PLAIN) {
+    const BoxInfo& bi = p->boxes[0];
+    sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1};
+    HIP_TRY(sbp::launch_plain(&p->master[0], p->d_recs, p->d_recs + 1, one, bi.var[sbp::kYFwd], bi.var[sbp::kXFwd],
+                              T + bi.tw_x, T + bi.tw_y, T + bi.tw_m, st, mk ? mark_cb : nullptr, mk));
+    return SBP_OK;
+  }
+  for (const Launch& l : p->launches) {
+    if (mk) mk->mark(kPassName[l.kind]);  // kinds stay distinct in the timing records
+    HIP_TRY(launch_one(p, l, st));
+  }
+  if (mk) mk->mark(nullptr);
   return SBP_OK;
 }
 
@@ -271,7 +354,164 @@ void destroy_graph(sbp_plan p) {
   p->graph = nullptr;
 }
 
+// workspace pointers in the record templates
+void bind_workspace(sbp_plan p) {
+  if (p->flags & SBP_FLAG_PLAIN) {
+    p->master[0].W = p->ws + p->boxes[0].ws2_off;
+    p->master[1].W = p->ws + p->boxes[0].ws_off;
+    return;
+  }
+  for (size_t b = 0; b < p->boxes.size(); ++b) p->master[b].W = p->ws + p->boxes[b].ws_off;
+}
+
+// fill a staging slot with the records of one solve and copy it to the device
+sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params,
+                         hipStream_t st) {
+  const int slot = p->slot;
+  p->slot = (p->slot + 1) % p->nslots;
+  if (p->slot_used[slot]) HIP_TRY(hipEventSynchronize(p->slot_ev[slot]));
+  sbp::BoxRec* hs = p->h_stage + (size_t)slot * p->nrec;
+  for (size_t r = 0; r < p->nrec; ++r) {
+    const size_t b = (p->flags & SBP_FLAG_PLAIN) ? 0 : r;
+    hs[r] = p->master[r];
+    const sbp::BoxGeom& g = p->boxes[b].g;
+    const sbp_shear& s = params[b];
+    double d = std::fmod(s.q * s.omega * g.lx * s.t, g.ly);
+    if (d < 0.0) d += g.ly;
+    if (d >= g.ly) d = 0.0;
+    hs[r].rho = rho[b];
+    hs[r].phi = phi[b];
+    hs[r].s = d / g.lx;
+    hs[r].fy = (d / g.ly) / (2.0 * g.nx);
+    hs[r].fourpiG = 4.0 * M_PI * s.G;
+    hs[r].scale = hs[r].fourpiG / ((double)g.nx * g.ny * g.m);
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_recs, hs, p->nrec * sizeof(sbp::BoxRec), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->slot_ev[slot], st));
+  p->slot_used[slot] = true;
+  return SBP_OK;
+}
+
+std::string describe_plan(sbp_plan p) {
+  std::string s = "{\"path\":\"";
+  bool any_fused = false, any_five = false;
+  for (const BoxInfo& b : p->boxes) (b.fused ? any_fused : any_five) = true;
+  s += (p->flags & SBP_FLAG_PLAIN) ? "plain" : (any_fused ? (any_five ? "mixed" : "fused-3pass") : "streaming-5pass");
+  s += "\",\"precision\":\"";
+  s += p->prec ? "fp32" : "fp64";
+  char buf[320];
+  snprintf(buf, sizeof buf,
+           "\",\"nbox\":%zu,\"launches\":%zu,\"graph\":%s,\"workspace_bytes\":%zu,\"tuning\":\"%s\"",
+           p->boxes.size(), (p->flags & SBP_FLAG_PLAIN) ? (size_t)13 : p->launches.size(),
+           (p->flags & SBP_FLAG_GRAPH) ? "true" : "false", p->ws_need, p->tune_source.c_str());
+  s += buf;
+  s += ",\"groups\":[";
+  for (size_t i = 0; i < p->launches.size(); ++i) {
+    const Launch& l = p->launches[i];
+    snprintf(buf, sizeof buf, "%s{\"pass\":\"%s\",\"len\":%d,\"variant\":%d,\"boxes\":%d,\"blocks\":%d}",
+             i ? "," : "", kPassName[l.kind], l.len, l.variant, l.n, l.blocks);
+    s += buf;
+  }
+  s += "]}";
+  return s;
+}
+
+sbp_status upload_groups(sbp_plan p) {
+  build_launches(p);
+  if (p->ints.size() > p->nints_cap) return fail(SBP_E_STATE, "group table overflow");
+  HIP_TRY(hipMemcpy(p->d_ints, p->ints.data(), p->ints.size() * sizeof(int), hipMemcpyHostToDevice));
+  p->describe = describe_plan(p);
+  return SBP_OK;
+}
+
 }  // namespace
+
+// --- plan access for the autotuner -------------------------------------------------------
+namespace sbp {
+
+int plan_prec(sbp_plan p) { return p->prec; }
+int plan_device(sbp_plan p) { return p->device; }
+std::vector<BoxInfo>& plan_boxes(sbp_plan p) { return p->boxes; }
+void plan_set_tune_source(sbp_plan p, const std::string& s) { p->tune_source = s; }
+
+// Time every launch group of the current variant assignment (reps solves after one warm-up) on
+// scratch buffers.  ms[i] is the mean time of launches()[i].
+sbp_status plan_time_groups(sbp_plan p, int reps, std::vector<Launch>& launches, std::vector<double>& ms) {
+  sbp_status us = upload_groups(p);
+  if (us != SBP_OK) return us;
+  std::vector<void*> bufs;
+  std::vector<const void*> rho;
+  std::vector<void*> phi;
+  std::vector<sbp_shear> sh;
+  auto release = [&]() {
+    for (void* b : bufs) hipFree(b);
+    bufs.clear();
+  };
+  for (const BoxInfo& bi : p->boxes) {
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bi.data_bytes) != hipSuccess) {
+      release();
+      return fail(SBP_E_NOMEM, "autotune scratch allocation");
+    }
+    bufs.push_back(a);
+    if (hipMalloc(&b, bi.data_bytes) != hipSuccess) {
+      release();
+      return fail(SBP_E_NOMEM, "autotune scratch allocation");
+    }
+    bufs.push_back(b);
+    hipMemset(a, 0, bi.data_bytes);
+    rho.push_back(a);
+    phi.push_back(b);
+    sh.push_back(sbp_shear{1.5, 1.0, 0.3, 1.0});
+  }
+  void* tws = nullptr;
+  if (hipMalloc(&tws, std::max<size_t>(p->ws_need, 256)) != hipSuccess) {
+    release();
+    return fail(SBP_E_NOMEM, "autotune workspace allocation");
+  }
+  bufs.push_back(tws);
+  char* saved_ws = p->ws;
+  p->ws = (char*)tws;
+  bind_workspace(p);
+  hipStream_t st = nullptr;
+  sbp_status res = SBP_OK;
+  std::vector<double> acc(p->launches.size(), 0.0);
+  std::vector<hipEvent_t> ev(p->launches.size() + 1);
+  for (auto& e : ev) hipEventCreate(&e);
+  for (int r = 0; r <= reps && res == SBP_OK; ++r) {
+    res = stage_records(p, rho.data(), phi.data(), sh.data(), st);
+    if (res != SBP_OK) break;
+    hipEventRecord(ev[0], st);
+    for (size_t i = 0; i < p->launches.size(); ++i) {
+      hipError_t e = launch_one(p, p->launches[i], st);
+      if (e != hipSuccess) {
+        res = fail(SBP_E_HIP, "autotune launch: %s", hipGetErrorString(e));
+        break;
+      }
+      hipEventRecord(ev[i + 1], st);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      res = fail(SBP_E_HIP, "autotune synchronise");
+      break;
+    }
+    for (size_t i = 0; r > 0 && i < p->launches.size(); ++i) {
+      float t = 0.f;
+      hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      acc[i] += t;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  p->ws = saved_ws;
+  if (p->ws) bind_workspace(p);
+  release();
+  if (res != SBP_OK) return res;
+  launches = p->launches;
+  ms.assign(acc.size(), 0.0);
+  for (size_t i = 0; i < acc.size(); ++i) ms[i] = acc[i] / reps;
+  return SBP_OK;
+}
+
+}  // namespace sbp
 
 extern "C" {
 
@@ -299,13 +539,14 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
     if (!boxes) return fail(SBP_E_ARG, "boxes is NULL");
     if (nbox < 1 || nbox > 4096) return fail(SBP_E_ARG, "nbox=%d outside [1, 4096]", nbox);
     if (precision != SBP_FP64 && precision != SBP_FP32) return fail(SBP_E_ARG, "unknown precision %d", precision);
-    if (flags & ~(SBP_FLAG_GRAPH | SBP_FLAG_AUTOTUNE | SBP_FLAG_PLAIN)) return fail(SBP_E_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(SBP_FLAG_GRAPH | SBP_FLAG_AUTOTUNE | SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS))
+      return fail(SBP_E_ARG, "unknown flags 0x%x", flags);
     if ((flags & SBP_FLAG_PLAIN) && (precision != SBP_FP64 || nbox != 1))
       return fail(SBP_E_ARG, "the plain path is FP64 and single-box");
     if (device < 0) return fail(SBP_E_ARG, "device=%d", device);
     const int prec = precision == SBP_FP32 ? 1 : 0;
     for (int i = 0; i < nbox; ++i) {
-      sbp_status st = validate_box(boxes[i], i, prec, flags);
+      sbp_status st = validate_box(boxes[i], i, prec);
       if (st != SBP_OK) return st;
     }
     // --- descriptors valid: from here on HIP is used
@@ -323,76 +564,124 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
     const size_t w = elem_size(prec);
     for (int i = 0; i < nbox; ++i) {
       const sbp_box& b = boxes[i];
-      BoxPlan bp;
+      BoxInfo bi;
       const int pad = b.pad == 0 ? 2 : b.pad;
       const double alpha = b.alpha == 0.0 ? 0.5 * pad : b.alpha;
-      bp.g = sbp::BoxGeom{b.nx, b.ny, b.nz, pad * b.nz, b.method, b.lx, b.ly, b.lz, alpha * b.lz};
-      bp.tw_x = tb.twiddle(b.nx, prec);
-      bp.tw_y = tb.twiddle(b.ny, prec);
-      bp.tw_m = tb.twiddle(pad * b.nz, prec);
-      bp.tw_m64 = tb.twiddle(pad * b.nz, 0);
+      bi.pad = pad;
+      bi.g = sbp::BoxGeom{b.nx, b.ny, b.nz, pad * b.nz, b.method, b.lx, b.ly, b.lz, alpha * b.lz};
+      bi.tw_x = tb.twiddle(b.nx, prec);
+      bi.tw_y = tb.twiddle(b.ny, prec);
+      bi.tw_m = tb.twiddle(pad * b.nz, prec);
+      bi.tw_m64 = tb.twiddle(pad * b.nz, 0);
       std::vector<long double> s2, ks, kz2;
-      ztables(bp.g, pad, s2, ks, kz2);
-      bp.zt64[0] = put_vec<double>(tb, s2);
-      bp.zt64[1] = put_vec<double>(tb, ks);
-      bp.zt64[2] = put_vec<double>(tb, kz2);
+      ztables(bi.g, pad, s2, ks, kz2);
+      bi.zt64[0] = put_vec<double>(tb, s2);
+      bi.zt64[1] = put_vec<double>(tb, ks);
+      bi.zt64[2] = put_vec<double>(tb, kz2);
       if (prec) {
-        bp.zt[0] = put_vec<float>(tb, s2);
-        bp.zt[1] = put_vec<float>(tb, ks);
-        bp.zt[2] = put_vec<float>(tb, kz2);
+        bi.zt[0] = put_vec<float>(tb, s2);
+        bi.zt[1] = put_vec<float>(tb, ks);
+        bi.zt[2] = put_vec<float>(tb, kz2);
       } else {
-        for (int k = 0; k < 3; ++k) bp.zt[k] = bp.zt64[k];
+        for (int k = 0; k < 3; ++k) bi.zt[k] = bi.zt64[k];
       }
+      sbp::default_variants(prec, bi.g, bi.var);
+      bi.fused = !(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS)) && sbp::fused_ok(bi.g);
       const size_t n = (size_t)b.nx * b.ny * b.nz;
-      bp.data_bytes = n * w;
+      bi.data_bytes = n * w;
       if (flags & SBP_FLAG_PLAIN) {
-        bp.ws_off = ws;
-        ws = align_up(ws + (size_t)b.nx * (b.ny / 2) * bp.g.m * 2 * sizeof(double));
-        bp.ws2_off = ws;
+        bi.ws_off = ws;
+        ws = align_up(ws + (size_t)b.nx * (b.ny / 2) * bi.g.m * 2 * sizeof(double));
+        bi.ws2_off = ws;
         ws = align_up(ws + n * sizeof(double));
-        bp.npartials = sbp::kPlainPartials;
+        bi.npartials = sbp::kPlainPartials;
       } else {
-        bp.ws_off = ws;
+        bi.ws_off = ws;
         ws = align_up(ws + n * w);  // nx * (ny/2) * nz complex
-        bp.npartials = sbp::yfwd_partials(prec, bp.g);
+        int most = 0;
+        for (int v = 0; v < sbp::kVariants; ++v) most = std::max(most, sbp::y_tiles(prec, bi.g, v));
+        most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, 0));
+        bi.npartials = most;
       }
-      bp.part_off = npart;
-      npart += 2 * (size_t)bp.npartials;
-      p->boxes.push_back(bp);
+      bi.part_off = npart;
+      npart += 2 * (size_t)bi.npartials;
+      p->boxes.push_back(bi);
     }
     p->ws_need = ws;
+    p->nrec = (flags & SBP_FLAG_PLAIN) ? 2 : (size_t)nbox;
 
     void* d = nullptr;
     if (hipMalloc(&d, std::max<size_t>(tb.host.size(), 256)) != hipSuccess)
       return fail(SBP_E_NOMEM, "table allocation (%zu bytes)", tb.host.size());
     p->d_tables = (char*)d;
     HIP_TRY(hipMemcpy(p->d_tables, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice));
-    const size_t aux = align_up(nbox * sizeof(sbp::SolveScalars)) + align_up(nbox * sizeof(sbp::SashaCoef)) +
-                       align_up(std::max<size_t>(npart, 2) * sizeof(double));
+
+    // group ints: per pass at most nbox groups; each box appears once per pass with 2 ints,
+    // plus one leading start per group
+    p->nints_cap = 8 * (3 * (size_t)nbox) + 8;
+    const size_t aux = align_up(p->nrec * sizeof(sbp::BoxRec)) + align_up(nbox * sizeof(sbp::SashaCoef)) +
+                       align_up(std::max<size_t>(npart, 2) * sizeof(double)) + align_up(p->nints_cap * sizeof(int));
     if (hipMalloc(&d, aux) != hipSuccess) return fail(SBP_E_NOMEM, "aux allocation (%zu bytes)", aux);
     p->d_aux = (char*)d;
-    p->d_sp = (sbp::SolveScalars*)p->d_aux;
-    p->d_coef = (sbp::SashaCoef*)(p->d_aux + align_up(nbox * sizeof(sbp::SolveScalars)));
-    p->d_partials = (double*)((char*)p->d_coef + align_up(nbox * sizeof(sbp::SashaCoef)));
+    char* cur = p->d_aux;
+    p->d_recs = (sbp::BoxRec*)cur;
+    cur += align_up(p->nrec * sizeof(sbp::BoxRec));
+    p->d_coef = (sbp::SashaCoef*)cur;
+    cur += align_up(nbox * sizeof(sbp::SashaCoef));
+    p->d_partials = (double*)cur;
+    cur += align_up(std::max<size_t>(npart, 2) * sizeof(double));
+    p->d_ints = (int*)cur;
+
+    // record templates
+    p->master.resize(p->nrec);
+    for (size_t r = 0; r < p->nrec; ++r) {
+      const size_t b = (flags & SBP_FLAG_PLAIN) ? 0 : r;
+      const BoxInfo& bi = p->boxes[b];
+      sbp::BoxRec& rec = p->master[r];
+      memset(&rec, 0, sizeof rec);
+      rec.g = bi.g;
+      rec.partials = p->d_partials + bi.part_off;
+      rec.npartials = 0;
+      rec.coef = p->d_coef + b;
+      for (int k = 0; k < 3; ++k) {
+        rec.zt[k] = p->d_tables + bi.zt[k];
+        rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
+      }
+    }
 
     p->nslots = 64;
     void* h = nullptr;
-    if (hipHostMalloc(&h, (size_t)p->nslots * nbox * sizeof(sbp::SolveScalars), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(&h, (size_t)p->nslots * p->nrec * sizeof(sbp::BoxRec), hipHostMallocDefault) != hipSuccess)
       return fail(SBP_E_NOMEM, "pinned staging allocation");
-    p->h_stage = (sbp::SolveScalars*)h;
+    p->h_stage = (sbp::BoxRec*)h;
     p->slot_ev.resize(p->nslots);
     p->slot_used.assign(p->nslots, false);
     for (auto& e : p->slot_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
-    char buf[512];
-    const BoxPlan& b0 = p->boxes[0];
-    snprintf(buf, sizeof buf,
-             "{\"path\":\"%s\",\"precision\":\"%s\",\"nbox\":%d,\"passes\":%d,\"graph\":%s,"
-             "\"box0\":[%d,%d,%d],\"pad_len\":%d,\"workspace_bytes\":%zu}",
-             (flags & SBP_FLAG_PLAIN) ? "plain" : "streaming-5pass", prec ? "fp32" : "fp64", nbox,
-             (flags & SBP_FLAG_PLAIN) ? 13 : 5, (flags & SBP_FLAG_GRAPH) ? "true" : "false", b0.g.nx, b0.g.ny,
-             b0.g.nz, b0.g.m, p->ws_need);
-    p->describe = buf;
+    if (flags & SBP_FLAG_PLAIN) {
+      p->master[1].g.nz = p->master[1].g.m;  // the padded spectrum seen as a box with nz = M
+      const BoxInfo& bi = p->boxes[0];
+      sbp::BoxGeom gp = bi.g;
+      gp.nz = gp.m;
+      // layout read by launch_plain: box_ids {0}, starts {0, y blocks}, then {0, x blocks}
+      const int lay[5] = {0, 0, sbp::y_tiles(0, bi.g, bi.var[sbp::kYFwd]), 0, sbp::x_tiles(0, gp, bi.var[sbp::kXFwd])};
+      HIP_TRY(hipMemcpy(p->d_ints, lay, sizeof lay, hipMemcpyHostToDevice));
+      p->describe = describe_plan(p.get());
+    } else {
+      if (flags & SBP_FLAG_AUTOTUNE) {
+        sbp_status ts = sbp::autotune(p.get());
+        if (ts != SBP_OK) return ts;
+      }
+      sbp_status us = upload_groups(p.get());
+      if (us != SBP_OK) return us;
+    }
+    // partial-sum slots used by the chosen y variant
+    for (size_t r = 0; r < p->nrec; ++r) {
+      const BoxInfo& bi = p->boxes[(flags & SBP_FLAG_PLAIN) ? 0 : r];
+      p->master[r].npartials = (flags & SBP_FLAG_PLAIN) ? sbp::kPlainPartials
+                               : bi.fused ? sbp::fused_ac_tiles(prec, bi.g, bi.var[sbp::kFA])
+                                          : sbp::y_tiles(prec, bi.g, bi.var[sbp::kYFwd]);
+    }
     *out = p.release();
     return SBP_OK;
   } catch (const std::bad_alloc&) {
@@ -412,7 +701,6 @@ sbp_status sbp_set_workspace(sbp_plan p, void* ptr, size_t bytes) {
   if (!p) return fail(SBP_E_ARG, "NULL plan");
   if (ptr == nullptr) {
     if (!p->ws_owned) p->ws = nullptr;
-    destroy_graph(p);
     return SBP_OK;
   }
   if (((uintptr_t)ptr) % kAlign) return fail(SBP_E_WORKSPACE, "workspace not %zu-byte aligned", kAlign);
@@ -424,7 +712,6 @@ sbp_status sbp_set_workspace(sbp_plan p, void* ptr, size_t bytes) {
   }
   p->ws = (char*)ptr;
   p->ws_owned = false;
-  destroy_graph(p);
   return SBP_OK;
 }
 
@@ -457,38 +744,20 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
       p->ws_owned = true;
     }
     for (size_t b = 0; b < nb; ++b)
-      if (overlap(phi[b], p->boxes[b].data_bytes, p->ws, p->ws_need))
-        return fail(SBP_E_ARG, "phi of box %zu overlaps the workspace", b);
+      if (overlap(phi[b], p->boxes[b].data_bytes, p->ws, p->ws_need) ||
+          overlap(rho[b], p->boxes[b].data_bytes, p->ws, p->ws_need))
+        return fail(SBP_E_ARG, "rho or phi of box %zu overlaps the workspace", b);
+    bind_workspace(p);
     hipStream_t st = (hipStream_t)stream;
-
-    // per-solve scalars -> pinned slot -> device
-    const int slot = p->slot;
-    p->slot = (p->slot + 1) % p->nslots;
-    if (p->slot_used[slot]) HIP_TRY(hipEventSynchronize(p->slot_ev[slot]));
-    sbp::SolveScalars* hs = p->h_stage + (size_t)slot * nb;
-    for (size_t b = 0; b < nb; ++b) {
-      const sbp::BoxGeom& g = p->boxes[b].g;
-      const sbp_shear& s = params[b];
-      double d = std::fmod(s.q * s.omega * g.lx * s.t, g.ly);
-      if (d < 0.0) d += g.ly;
-      if (d >= g.ly) d = 0.0;
-      hs[b].s = d / g.lx;
-      hs[b].fy = (d / g.ly) / (2.0 * g.nx);
-      hs[b].fourpiG = 4.0 * M_PI * s.G;
-      hs[b].scale = hs[b].fourpiG / ((double)g.nx * g.ny * g.m);
-    }
-    HIP_TRY(hipMemcpyAsync(p->d_sp, hs, nb * sizeof(sbp::SolveScalars), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(p->slot_ev[slot], st));
-    p->slot_used[slot] = true;
+    sbp_status ss = stage_records(p, rho, phi, params, st);
+    if (ss != SBP_OK) return ss;
 
     if (p->flags & SBP_FLAG_GRAPH) {
-      bool same = p->gexec && p->g_ws == p->ws;
-      for (size_t b = 0; same && b < nb; ++b) same = p->g_rho[b] == rho[b] && p->g_phi[b] == phi[b];
-      if (!same) {
-        destroy_graph(p);
+      if (!p->gexec) {
+        // the launches read everything per-solve from the device records: capture once
         if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        sbp_status es = enqueue(p, rho, phi, p->cap_stream, nullptr);
+        sbp_status es = enqueue(p, p->cap_stream, nullptr);
         hipGraph_t gr = nullptr;
         hipError_t ce = hipStreamEndCapture(p->cap_stream, &gr);
         if (es != SBP_OK) {
@@ -498,9 +767,6 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
         if (ce != hipSuccess) return fail(SBP_E_HIP, "graph capture: %s", hipGetErrorString(ce));
         p->graph = gr;
         HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
-        p->g_rho.assign(rho, rho + nb);
-        p->g_phi.assign(phi, phi + nb);
-        p->g_ws = p->ws;
       }
       Marker mk{p, st};
       if (p->prof) mk.mark("graph");
@@ -509,7 +775,7 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
       return SBP_OK;
     }
     Marker mk{p, st};
-    return enqueue(p, rho, phi, st, p->prof ? &mk : nullptr);
+    return enqueue(p, st, p->prof ? &mk : nullptr);
   } catch (const std::bad_alloc&) {
     return fail(SBP_E_NOMEM, "host allocation failed");
   } catch (...) {
@@ -546,7 +812,7 @@ sbp_status sbp_profile_read(sbp_plan p, const char** names, int64_t* launches, d
                             int32_t* count) {
   if (!p || !count) return fail(SBP_E_ARG, "NULL argument");
   hipSetDevice(p->device);
-  // events are shared between consecutive records; destroy each once
+  // events are shared between consecutive records; recycle each once
   std::vector<hipEvent_t> seen;
   for (auto& r : p->pending) {
     HIP_TRY(hipEventSynchronize(r.b));

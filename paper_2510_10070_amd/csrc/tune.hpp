@@ -1,0 +1,56 @@
+// Plan internals shared with the autotuner.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/sbp.h"
+#include "sbp_internal.hpp"
+
+namespace sbp {
+
+// 0-4: the five streaming passes; 5-7: the fused three-pass schedule
+enum PassKind { kYFwd = 0, kXFwd = 1, kZ = 2, kXInv = 3, kYInv = 4, kFA = 5, kFB = 6, kFC = 7 };
+constexpr int kKinds = 8;
+// position of each kind in the solve sequence (boxes are independent, so kinds of the same phase
+// may run in any order)
+constexpr int kPhase[kKinds] = {0, 1, 2, 3, 4, 0, 2, 4};
+
+// one kernel launch of the solve sequence: a group of boxes sharing a kernel shape
+struct Launch {
+  int kind = 0, len = 0, variant = 0, q = 0, a = 0;
+  int blocks = 0;
+  size_t ints_off = 0;  // offset (in ints) of box_ids[n] then starts[n+1] in the group int block
+  int n = 0;
+  size_t tw = 0, tw64 = 0;  // table offsets
+};
+
+struct BoxInfo {
+  BoxGeom g;
+  int pad = 2;
+  size_t tw_x = 0, tw_y = 0, tw_m = 0, tw_m64 = 0;  // offsets into the table block
+  size_t zt[3] = {0, 0, 0}, zt64[3] = {0, 0, 0};
+  size_t ws_off = 0;   // half spectrum (plain: padded spectrum)
+  size_t ws2_off = 0;  // plain: unpadded half spectrum
+  size_t part_off = 0;
+  int npartials = 0;
+  size_t data_bytes = 0;
+  int var[kKinds] = {1, 1, 1, 1, 1, 0, 0, 0};  // tile variant per pass kind
+  bool fused = false;                           // three-pass schedule for this box
+};
+
+sbp_status fail(sbp_status st, const char* fmt, ...);
+
+// built-in variant choice (measured on MI355X) for a box
+void default_variants(int prec, const BoxGeom& g, int var[kKinds]);
+// time the variants of every pass and keep the fastest per (pass, length); cached on disk
+sbp_status autotune(sbp_plan p);
+
+// plan access for the autotuner
+int plan_prec(sbp_plan p);
+int plan_device(sbp_plan p);
+std::vector<BoxInfo>& plan_boxes(sbp_plan p);
+void plan_set_tune_source(sbp_plan p, const std::string& s);
+sbp_status plan_time_groups(sbp_plan p, int reps, std::vector<Launch>& launches, std::vector<double>& ms);
+
+}  // namespace sbp

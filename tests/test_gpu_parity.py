@@ -141,3 +141,90 @@ def test_argument_errors_on_device():
         plan.set_workspace(small)
     assert e.value.status == 4
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_groups_and_autotune(precision, tmp_path, monkeypatch):
+    # several boxes share each kernel shape (one launch per group), uneven sizes, per-box shear
+    monkeypatch.setenv("SBP_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    shapes = [(32, 32, 16), (16, 32, 32), (32, 32, 16), (16, 32, 32), (32, 16, 16), (32, 32, 16)]
+    boxes = [_box(s + (1.0, 1.0 + 0.1 * i, 0.8, 2, 0.0), "vgf" if i % 3 else "sasha") for i, s in enumerate(shapes)]
+    rhos = [lognormal_density(s, 0.8, 0.2, seed=40 + i) for i, s in enumerate(shapes)]
+    shears = [(1.5 if i % 2 else 2.0, 1.0, 0.13 * i, 1.0) for i in range(len(shapes))]
+    # the five-pass kernels come in several tile variants (the autotuner times them; the second
+    # autotuned plan reads the cache); the fused schedule has one tile shape per length
+    for autotune, five in ((False, False), (True, True), (True, True), (True, False)):
+        got, used = gpu_solve(boxes, rhos, shears, precision, autotune=autotune, five_pass=five)
+        for b, g, u, s in zip(boxes, got, used, shears):
+            assert rel_l2(g, oracle_solve(b, u, s)) <= TOL[precision]
+    assert (tmp_path / "tune.txt").exists()
+
+
+def test_graph_replay_with_new_pointers():
+    import torch
+
+    from paper_2510_10070_amd import Box, Plan, Shear
+
+    shape = (32, 16, 16)
+    plan = Plan(Box(*shape, 1.0, 1.0, 1.0), precision="fp64", graph=True)
+    ref_plan = Plan(Box(*shape, 1.0, 1.0, 1.0), precision="fp64")
+    for i in range(3):
+        rho = torch.tensor(lognormal_density(shape, 1.0, 0.2, seed=60 + i), dtype=torch.float64, device="cuda:0")
+        out = torch.empty_like(rho)
+        ref = torch.empty_like(rho)
+        plan.solve(rho, out, Shear(t=0.2 * i))
+        ref_plan.solve(rho, ref, Shear(t=0.2 * i))
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    plan.close()
+    ref_plan.close()
+
+
+# shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 8, 16}, y up to 512,
+# padded z from 32 to 512, P = 4 (power-of-two padded z lengths leave no ragged z chunk)
+FUSED_SHAPES = [
+    (16, 16, 16, 1.0, 1.0, 1.0, 2, 0.0),
+    (32, 64, 32, 1.2, 0.8, 1.0, 2, 0.0),
+    (64, 32, 48, 1.0, 1.0, 1.0, 2, 0.0),
+    (128, 16, 16, 2.0, 1.0, 1.0, 4, 1.5),
+    (256, 16, 16, 1.0, 1.0, 1.0, 2, 0.0),
+    (16, 512, 16, 1.0, 4.0, 1.0, 2, 0.0),
+    (16, 16, 256, 1.0, 1.0, 2.0, 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["vgf", "sasha"])
+@pytest.mark.parametrize("shape", FUSED_SHAPES, ids=lambda s: "x".join(map(str, s[:3])) + f"_P{s[6]}")
+def test_fused_schedule_parity(shape, method, precision):
+    box = _box(shape, method)
+    rho = lognormal_density(shape[:3], shape[5], 0.2 * shape[5], seed=sum(shape[:3]) + 101)
+    shear = (1.5, 1.0, 0.83, 0.7)
+    got, used = gpu_solve(box, rho, shear, precision)
+    ref = oracle_solve(box, used[0], shear)
+    err = rel_l2(got[0], ref)
+    five, _ = gpu_solve(box, used[0], shear, precision, five_pass=True)
+    err5 = rel_l2(five[0], ref)
+    print(f"{shape} {method} {precision}: fused {err:.3e} five-pass {err5:.3e}")
+    assert err <= TOL[precision], err
+    assert err5 <= TOL[precision], err5
+
+
+def test_fused_is_selected_and_mixed_schedules():
+    from paper_2510_10070_amd import Box, Plan
+
+    for boxes, want in (([Box(32, 32, 32, 1.0, 1.0, 1.0)], "fused-3pass"),
+                        ([Box(32, 32, 32, 1.0, 1.0, 1.0), Box(48, 32, 16, 1.0, 1.0, 1.0)], "mixed")):
+        plan = Plan(boxes, precision="fp32")
+        d = plan.describe()
+        plan.close()
+        assert want in str(d), d
+    # one plan holding a fused box, a five-pass box and a SASHA fused box
+    shapes = [(32, 32, 32), (48, 32, 16), (64, 16, 16)]
+    boxes = [_box(s + (1.0, 1.0, 1.0, 2, 0.0), m) for s, m in zip(shapes, ["vgf", "vgf", "sasha"])]
+    rhos = [lognormal_density(s, 1.0, 0.2, seed=70 + i) for i, s in enumerate(shapes)]
+    shears = [(1.5, 1.0, 0.1 + 0.4 * i, 1.0) for i in range(3)]
+    for prec in ("fp64", "fp32"):
+        got, used = gpu_solve(boxes, rhos, shears, prec, graph=True)
+        for b, g, u, s in zip(boxes, got, used, shears):
+            assert rel_l2(g, oracle_solve(b, u, s)) <= TOL[prec]
