@@ -55,6 +55,34 @@ def time_plan(plan, rho, phi, shear, steps: int, warmup: int, profile: bool):
     return ms, kernels
 
 
+# (name, precision, plain path, graph replay)
+LEGS = (("fp32", "fp32", False, True), ("fp64", "fp64", False, True), ("plain_fp64", "fp64", True, False),
+        ("fp32_direct", "fp32", False, False), ("fp64_direct", "fp64", False, False))
+
+
+def copy_calibration(mib: int, steps: int) -> int:
+    """A plain device-to-device copy of known size, for scaling hardware byte counters."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nbytes = 2 * n * 4
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": round(ms, 5),
+                      "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,11 +90,20 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-samples", type=int, default=2)
+    ap.add_argument("--only", choices=[leg[0] for leg in LEGS],
+                    help="time one leg and print its kernel split (for profiler runs)")
+    ap.add_argument("--schedule", choices=["auto", "fused", "five_pass"], default="auto",
+                    help="pass schedule of the non-plain legs (auto: the library's choice per precision)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="time a plain device copy of this many MiB instead (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         return 2
+
+    if args.copy_mib:
+        return copy_calibration(args.copy_mib, args.steps)
 
     import numpy as np
     import torch
@@ -85,13 +122,13 @@ def main() -> int:
 
     res = {}
     phis = {}
-    legs = (("fp32", "fp32", False, True), ("fp64", "fp64", False, True), ("plain_fp64", "fp64", True, False),
-            ("fp32_direct", "fp32", False, False), ("fp64_direct", "fp64", False, False))
+    legs = [leg for leg in LEGS if args.only in (None, leg[0])]
     for leg, prec, plain, graph in legs:
         dt = torch.float32 if prec == "fp32" else torch.float64
         rho = torch.tensor(rho64, dtype=dt, device="cuda:0")
         phi = torch.empty_like(rho)
-        plan = Plan(box, precision=prec, plain=plain, graph=graph, autotune=not plain)
+        plan = Plan(box, precision=prec, plain=plain, graph=graph, autotune=not plain,
+                    schedule="auto" if plain else args.schedule)
         steps = args.steps if not plain else max(10, args.steps // 4)
         log(f"timing {leg}: {args.warmup} warm-up + {steps} steps")
         # graph legs are timed clean (the library times a graph as one unit); the per-kernel
@@ -106,6 +143,13 @@ def main() -> int:
         plan.close()
         del rho, phi
         torch.cuda.empty_cache()
+
+    if args.only:
+        r = res[args.only]
+        print(json.dumps({"leg": args.only, "ms_per_step": round(r["ms"], 5), "solves_per_s": round(r["solves_per_s"], 1),
+                          "kernels_us": {kk: round(v[1] / v[0] * 1e3, 2) for kk, v in r["kernels"].items()},
+                          "schedule": r["describe"]}), flush=True)
+        return 0
 
     # accuracy against the FP64 CPU oracle, and the oracle's own throughput on this host
     cpu = None

@@ -63,10 +63,15 @@ typedef enum { SBP_VGF = 0, SBP_SASHA = 1 } sbp_method;
 #define SBP_FLAG_AUTOTUNE 0x2u /* time the tile variants at plan creation and keep the fastest */
 #define SBP_FLAG_PLAIN 0x4u    /* unfused reference path: padded spectrum in HBM, one kernel per
                                   step (pad, each axis transform, Green multiply, extract, ...) */
-#define SBP_FLAG_FIVE_PASS 0x8u /* one streaming pass per axis and direction (five HBM round trips
-                                   of the half spectrum) even where the fused three-pass schedule
-                                   applies (power-of-two 16 <= nx <= 256, 16 <= ny <= 512,
-                                   32 <= pad*nz <= 512) */
+#define SBP_FLAG_FIVE_PASS 0x8u /* one streaming pass per axis and direction: five HBM round trips
+                                   of the half spectrum */
+#define SBP_FLAG_FUSED 0x10u    /* fused three-pass schedule (x split into 16 x nx/16, four-step):
+                                   three HBM round trips of the half spectrum.  It applies to
+                                   power-of-two 16 <= nx <= 256, 16 <= ny <= 512 and
+                                   32 <= pad*nz <= 512; other boxes of the plan run five-pass.
+                                   Without either schedule flag a plan picks per precision: fused
+                                   for SBP_FP32, five-pass for SBP_FP64 (the faster on gfx950).
+                                   Both flags together are SBP_E_ARG. */
 
 /* Geometry and method of one box.
  *   nx, ny: horizontal cells, each in {8,12,16,24,32,48,64,96,128,192,256,384,512,768,1024};
@@ -95,7 +100,8 @@ typedef struct {
  * precision: sbp_precision.  SBP_FP32 computes the transforms in float with twiddles,
  *   Green's-function scalars, shear phases and the k = 0 pencil evaluated in double.
  * device: HIP device ordinal; the plan's tables are allocated there.
- * flags: SBP_FLAG_*; SBP_FLAG_PLAIN requires SBP_FP64 and nbox == 1.
+ * flags: SBP_FLAG_*; SBP_FLAG_PLAIN requires SBP_FP64 and nbox == 1 and excludes the
+ *   schedule flags.
  * On success *out receives the plan; on failure *out is set to NULL.
  * Returns SBP_E_ARG / SBP_E_SIZE for invalid descriptors before any HIP call is made. */
 sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision, int32_t device,

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 from typing import Optional, Sequence, Union
 
 from . import _lib
-from ._lib import SBP_FLAG_AUTOTUNE, SBP_FLAG_FIVE_PASS, SBP_FLAG_GRAPH, SBP_FLAG_PLAIN, SbpBox, SbpShear
+from ._lib import (SBP_FLAG_AUTOTUNE, SBP_FLAG_FIVE_PASS, SBP_FLAG_FUSED, SBP_FLAG_GRAPH, SBP_FLAG_PLAIN, SbpBox,
+                   SbpShear)
 
 __all__ = ["Box", "Shear", "Plan", "SbpError", "load_library"]
 
@@ -73,13 +74,14 @@ class Plan:
     """A solve plan for one or more boxes (sbp_plan_create ... sbp_plan_destroy)."""
 
     def __init__(self, boxes: Union[Box, Sequence[Box]], precision: str = "fp32", device: int = 0,
-                 graph: bool = False, autotune: bool = False, plain: bool = False, five_pass: bool = False):
+                 graph: bool = False, autotune: bool = False, plain: bool = False, schedule: str = "auto"):
         self._lib = _lib.load()
         self.boxes = [boxes] if isinstance(boxes, Box) else list(boxes)
         self.precision = precision
         prec = {"fp64": _lib.SBP_FP64, "fp32": _lib.SBP_FP32}.get(precision, -1)
         flags = ((SBP_FLAG_GRAPH if graph else 0) | (SBP_FLAG_AUTOTUNE if autotune else 0)
-                 | (SBP_FLAG_PLAIN if plain else 0) | (SBP_FLAG_FIVE_PASS if five_pass else 0))
+                 | (SBP_FLAG_PLAIN if plain else 0)
+                 | {"auto": 0, "fused": SBP_FLAG_FUSED, "five_pass": SBP_FLAG_FIVE_PASS}.get(schedule, 0x8000))
         arr = (SbpBox * len(self.boxes))(*[b.to_c() for b in self.boxes])
         h = ctypes.c_void_p()
         self._h = None

@@ -326,6 +326,20 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
   }
 };
 
+// Barrier policies of the engine.  BlockSync: the tile is shared by the whole workgroup.
+// WaveSync: the tile belongs to one wavefront; its LDS operations complete in issue order, so
+// only the compiler must be kept from moving accesses across the exchange point.
+struct BlockSync {
+  static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  static __device__ __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // Full transform of every pencil in the tile.
 //   src(elem, b) -> cplx: input element of transform b (read by stage 0 only);
 //   dst(elem, b, v): output element of transform b (written by the last stage only).
@@ -334,17 +348,17 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
 // next write to it.  On return without DST_LDS the last stage has read `buf`: the caller must
 // barrier before writing it again; with DST_LDS the caller must barrier before reading it.
 template <typename T, int N, class RL, class L, int NT, int D, bool SRC_LDS, bool DST_LDS, int S = 0, int Q = 1,
-          class Src, class Dst>
+          class Sy = BlockSync, class Src, class Dst>
 __device__ __forceinline__ void fft_run(cplx<T>* buf, const cplx<T>* tw, int tid, Src&& src, Dst&& dst) {
   using St = Stage<T, N, RL, S, L, NT, D>;
   constexpr bool LAST = S == RL::n - 1;
   cplx<T> v[St::PER][St::R];
   if constexpr (S == 0) {
     St::read_fn(v, tid, src);
-    if constexpr (SRC_LDS && (!LAST || DST_LDS)) __syncthreads();
+    if constexpr (SRC_LDS && (!LAST || DST_LDS)) Sy::sync();
   } else {
     St::read_lds(v, buf, tid);
-    if constexpr (!LAST || DST_LDS) __syncthreads();
+    if constexpr (!LAST || DST_LDS) Sy::sync();
   }
   St::twiddle_dft(v, tw, tid);
   if constexpr (LAST) {
@@ -352,8 +366,8 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, const cplx<T>* tw, int tid
     St::template write_fn<(St::R % Q == 0) ? St::R / Q : St::R>(v, tid, dst);
   } else {
     St::write_lds(v, buf, tid);
-    __syncthreads();
-    fft_run<T, N, RL, L, NT, D, SRC_LDS, DST_LDS, S + 1, Q>(buf, tw, tid, src, dst);
+    Sy::sync();
+    fft_run<T, N, RL, L, NT, D, SRC_LDS, DST_LDS, S + 1, Q, Sy>(buf, tw, tid, src, dst);
   }
 }
 
@@ -363,7 +377,7 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, const cplx<T>* tw, int tid
 //   dst(elem, b, v) (inverse outputs).
 // Q > 1 (zero padding by Q): forward inputs at or above N/Q are zero and inverse outputs at or
 // above N/Q are discarded; both are dropped at compile time where the radix allows.
-template <typename T, int N, class L, int NT, int S, int Q = 1, class Src, class Op, class Dst>
+template <typename T, int N, class L, int NT, int S, int Q = 1, class Sy = BlockSync, class Src, class Op, class Dst>
 __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, int tid, Src&& src, Op&& op,
                                                Dst&& dst) {
   using RF = typename Fwd<N>::L;
@@ -377,12 +391,12 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, 
       St::template read_fn<(St::R % Q == 0) ? St::R / Q : St::R>(v, tid, src);
     } else {
       St::read_lds(v, buf, tid);
-      __syncthreads();
+      Sy::sync();
     }
     St::twiddle_dft(v, tw, tid);
     St::write_lds(v, buf, tid);
-    __syncthreads();
-    fft_fwd_op_inv<T, N, L, NT, S + 1, Q>(buf, tw, tid, src, op, dst);
+    Sy::sync();
+    fft_fwd_op_inv<T, N, L, NT, S + 1, Q, Sy>(buf, tw, tid, src, op, dst);
   } else {
     using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
     using Si = Stage<T, N, RI, 0, L, NT, +1>;
@@ -392,7 +406,7 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, 
       Sf::template read_fn<(Sf::R % Q == 0) ? Sf::R / Q : Sf::R>(v, tid, src);
     } else {
       Sf::read_lds(v, buf, tid);
-      __syncthreads();
+      Sy::sync();
     }
     Sf::twiddle_dft(v, tw, tid);
     // last forward stage: outputs j + r*NBF (base = j since j < NS = NBF)
@@ -410,8 +424,8 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, 
       Si::template write_fn<(Si::R % Q == 0) ? Si::R / Q : Si::R>(v, tid, dst);
     } else {
       Si::write_lds(v, buf, tid);
-      __syncthreads();
-      fft_run<T, N, RI, L, NT, +1, false, false, 1, Q>(buf, tw, tid, src, dst);
+      Sy::sync();
+      fft_run<T, N, RI, L, NT, +1, false, false, 1, Q, Sy>(buf, tw, tid, src, dst);
     }
   }
 }

@@ -15,15 +15,9 @@
 namespace sbp {
 
 constexpr int kFusedAC = 512;  // threads of passes A and C
-constexpr int kFusedB = 256;   // threads of pass B
 
 // real z cells per pass-A/C tile: variant 1 = 64-byte rows, variant 0 = 32-byte rows
 template <typename T, int V> constexpr int fa_zc() { return (V ? 64 : 32) / (int)sizeof(T); }
-// pencils per z-transform group in pass B (LDS budget)
-template <typename T, int M, int B> constexpr int fb_group() {
-  constexpr int g = 2048 / M;  // enough butterflies to keep all 256 threads busy
-  return g >= B ? B : (g < 1 ? 1 : g);
-}
 
 // four-step split used by the fused schedule: B = 16 pencils per pass-B block, A = Nx/16
 constexpr int kFusedB16 = 16;
@@ -325,26 +319,44 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
 }
 
 // ------------------------------------------------------------------------------------------
-// Pass B: one block per (k1, my).  B-point DFT across the j pencils in registers (each thread
-// owns z positions), pencils parked in LDS, then groups of G pencils go through the padded z
-// transform / Green multiply / inverse (Kx = k1 + A k2), then the inverse B-point DFT.
+// Pass B: one block per (k1, my).  The B-point DFT across the j pencils runs in registers
+// (each thread owns z positions) and parks the B pencils in LDS.  Then every wavefront takes
+// whole pencils: the padded z transform, the Green multiply for Kx = k1 + A k2 and the inverse
+// run in its registers and a wavefront-private LDS exchange tile, with no workgroup barrier.
+// A final barrier, and the inverse B-point DFT goes back to HBM.
+
+// pencils one wavefront transforms side by side (8 points per lane) and wavefronts per block
+template <int M> constexpr int fb_pw() { return M >= 512 ? 1 : 512 / M; }
+template <int M, int B> constexpr int fb_waves() {
+  constexpr int w = M >= 512 ? 8 : 4;  // 512: two blocks of eight wavefronts fit the 160 KB LDS
+  return B / fb_pw<M>() < w ? B / fb_pw<M>() : w;
+}
+template <int M, int B> constexpr int fb_threads() { return 64 * fb_waves<M, B>(); }
 
 template <typename T, int M, int B, int Q>
-__global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                                const cplx<T>* __restrict__ twm, const double2* __restrict__ twm64,
-                                                int A) {
-  constexpr int NT = kFusedB;
+__global__ __launch_bounds__(512) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                            const cplx<T>* __restrict__ twm, const double2* __restrict__ twm64,
+                                            int A) {
+  constexpr int PW = fb_pw<M>();
+  constexpr int WV = fb_waves<M, B>();
+  constexpr int NT = 64 * WV;
   constexpr int NZ = M / Q;
-  constexpr int G = fb_group<T, M, B>();
   constexpr bool kF32 = std::is_same<T, float>::value;
   using LT = Tile<B, 1, NZ, false>;  // parked pencils: element z of pencil k2
-  using LX = Tile<G, 1, M, false>;   // z-transform exchange tile
+  using LW = Tile<PW, 1, M, false>;  // one wavefront's exchange tile
+  constexpr int XS = lds_slots(PW * M);
   __shared__ cplx<T> tile[lds_slots(B * NZ)];
-  __shared__ cplx<T> xbuf[lds_slots(G * M)];
+  __shared__ cplx<T> xbuf[WV * XS];
   __shared__ cplx<T> tw[M];
-  __shared__ T pa0[G], pe[G], pik[G], pk2[G];
-  __shared__ int pzero[G];
-  __shared__ double2 d0[kF32 ? NZ : 1];  // float plans: the k = 0 pencil input in double
+  __shared__ T pa0[B], pe[B], pik[B], pk2[B];
+  __shared__ int pzero[B];
+  // block-0 work before the wavefront transforms borrows xbuf: the double k = 0 exchange
+  // tile, the k = 0 pencil input in double and the SASHA reduction
+  constexpr int X64 = lds_slots(M);
+  static_assert((X64 + NZ) * 16 + 2 * NT * 8 <= WV * XS * (int)sizeof(cplx<T>), "block-0 scratch must fit");
+  double2* dbuf = reinterpret_cast<double2*>(xbuf);
+  double2* d0 = dbuf + X64;
+  double* red = reinterpret_cast<double*>(d0 + NZ);
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -355,11 +367,31 @@ __global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __re
   const bool sasha = g.method == 1;
   const double scale = br->scale;
   cplx<T>* base = static_cast<cplx<T>*>(br->W) + (size_t)t * B * NZ;
-  const T* zs2 = static_cast<const T*>(br->zt[0]);
-  const T* zks = static_cast<const T*>(br->zt[1]);
-  const T* zkz2 = static_cast<const T*>(br->zt[2]);
   const bool own0 = kF32 && t == 0;  // this block holds Kx = Ky = 0 (pencil k2 = 0)
   load_twiddles<T, M, NT>(tw, twm, tid);
+
+  // Green's-function scalars of the B pencils (double, rounded once)
+  if (tid < B) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const double Ky = (two_pi / g.ly) * my;
+    const int mx = k1 + A * tid;
+    const int sx = mx < g.nx / 2 ? mx : mx - g.nx;
+    const double kx = (two_pi / g.lx) * sx + br->s * Ky;
+    const double kk2 = kx * kx + Ky * Ky;
+    const double k = sqrt(kk2);
+    const int zero = (mx == 0 && my == 0);
+    pzero[tid] = zero;
+    pk2[tid] = (T)kk2;
+    if (!zero && !sasha) {
+      pa0[tid] = (T)(-expm1(-k * g.L) * scale);
+      pe[tid] = (T)(exp(-k * g.L) * scale);
+      pik[tid] = (T)(1.0 / k);
+    } else {
+      pa0[tid] = T(0);
+      pe[tid] = T(0);
+      pik[tid] = T(0);
+    }
+  }
 
   // B-point DFT across j for each z
   for (int z = tid; z < NZ; z += NT) {
@@ -373,7 +405,7 @@ __global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __re
         sx += (double)v[jj].x;
         sy += (double)v[jj].y;
       }
-      d0[kF32 ? z : 0] = make_double2(sx, sy);
+      d0[z] = make_double2(sx, sy);
     }
     Dft<B, -1, T>::run(v);
 #pragma unroll
@@ -382,24 +414,23 @@ __global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __re
 
   // SASHA: <rho> and the centre of mass from the pass-A partial sums (fixed order)
   if (sasha && t == 0) {
-    __shared__ double red[2][NT];
     double a = 0.0, b = 0.0;
     for (int i = tid; i < br->npartials; i += NT) {
       a += br->partials[2 * i];
       b += br->partials[2 * i + 1];
     }
-    red[0][tid] = a;
-    red[1][tid] = b;
+    red[tid] = a;
+    red[NT + tid] = b;
     __syncthreads();
     for (int o = NT / 2; o > 0; o >>= 1) {
       if (tid < o) {
-        red[0][tid] += red[0][tid + o];
-        red[1][tid] += red[1][tid + o];
+        red[tid] += red[tid + o];
+        red[NT + tid] += red[NT + tid + o];
       }
       __syncthreads();
     }
     if (tid == 0) {
-      const double s0 = red[0][0], s1 = red[1][0];
+      const double s0 = red[0], s1 = red[NT];
       SashaCoef c;
       c.c2 = 0.0;
       c.c1 = 0.0;
@@ -413,11 +444,10 @@ __global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __re
   }
   __syncthreads();
 
-  // float plans: the k = 0 pencil in double, exchanged through xbuf, result parked in the tile
+  // float plans: the k = 0 pencil in double (block-wide), result parked in the tile
   if constexpr (kF32) {
     if (t == 0) {
       using L1 = Tile<1, 1, M, false>;
-      double2* dbuf = reinterpret_cast<double2*>(xbuf);
       const double* z64s2 = br->zt64[0];
       const double* z64ks = br->zt64[1];
       const double* z64kz2 = br->zt64[2];
@@ -436,50 +466,32 @@ __global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __re
           [&](int e, int, double2 v) {
             if (e < NZ) tile[LT::at(e, 0)] = make_float2((float)v.x, (float)v.y);
           });
-      __syncthreads();
+      __syncthreads();  // xbuf is handed to the wavefronts
     }
   }
 
-  const int nx = g.nx;
-  const double two_pi = 6.283185307179586476925286766559;
-  const double Ky = (two_pi / g.ly) * my;
+  // wavefront-private padded z transforms, Green multiply and inverse
+  const T* zt = static_cast<const T*>(br->zt);
   const T L_ = (T)g.L;
   const T sc = (T)scale;
+  const int wave = tid >> 6, lane = tid & 63;
+  cplx<T>* xw = xbuf + wave * XS;
 #pragma unroll 1
-  for (int g0 = 0; g0 < B; g0 += G) {
-    if (tid < G) {
-      const int k2 = g0 + tid;
-      const int mx = k1 + A * k2;
-      const int sx = mx < nx / 2 ? mx : mx - nx;
-      const double kx = (two_pi / g.lx) * sx + br->s * Ky;
-      const double kk2 = kx * kx + Ky * Ky;
-      const double k = sqrt(kk2);
-      const int zero = (mx == 0 && my == 0);
-      pzero[tid] = zero;
-      pk2[tid] = (T)kk2;
-      if (!zero && !sasha) {
-        pa0[tid] = (T)(-expm1(-k * g.L) * scale);
-        pe[tid] = (T)(exp(-k * g.L) * scale);
-        pik[tid] = (T)(1.0 / k);
-      } else {
-        pa0[tid] = T(0);
-        pe[tid] = T(0);
-        pik[tid] = T(0);
-      }
-    }
-    __syncthreads();
-    fft_fwd_op_inv<T, M, LX, NT, 0, Q>(
-        xbuf, tw, tid,
+  for (int p0 = wave * PW; p0 < B; p0 += WV * PW) {
+    fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
+        xw, tw, lane,
         [&](int e, int p) {
-          return (e < NZ && !(own0 && g0 + p == 0)) ? tile[LT::at(e, g0 + p)] : mk<T>(T(0), T(0));
+          return (e < NZ && !(own0 && p0 + p == 0)) ? tile[LT::at(e, p0 + p)] : mk<T>(T(0), T(0));
         },
         [&](int mz, int p, cplx<T>& v) {
-          const T s2 = zs2[mz], ks = zks[mz], kz2 = zkz2[mz];
+          const int k2 = p0 + p;
+          const ZRow<T> zr = zrow(zt, mz);
+          const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
           T gk;
           if (sasha) {
-            gk = (pzero[p] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[p] + kz2);
-          } else if (!pzero[p]) {
-            gk = -(pa0[p] + pe[p] * (s2 + pik[p] * ks)) * fast_rcp(pk2[p] + kz2);
+            gk = (pzero[k2] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[k2] + kz2);
+          } else if (!pzero[k2]) {
+            gk = -(pa0[k2] + pe[k2] * (s2 + pik[k2] * ks)) * fast_rcp(pk2[k2] + kz2);
           } else {
             gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
           }
@@ -487,10 +499,11 @@ __global__ __launch_bounds__(kFusedB) void k_fb(GroupArgs ga, const BoxRec* __re
           v.y *= gk;
         },
         [&](int e, int p, cplx<T> v) {
-          if (e < NZ && !(own0 && g0 + p == 0)) tile[LT::at(e, g0 + p)] = v;
+          if (e < NZ && !(own0 && p0 + p == 0)) tile[LT::at(e, p0 + p)] = v;
         });
-    __syncthreads();  // pencil results parked; scalars and xbuf reused by the next group
+    WaveSync::sync();  // the exchange tile is rewritten by this wavefront's next pencils
   }
+  __syncthreads();
 
   // inverse B-point DFT across k2, store
   for (int z = tid; z < NZ; z += NT) {

@@ -16,6 +16,21 @@
 
 namespace sbp {
 
+// one row {1 - cos(kz L), kz sin(kz L), kz^2} of the z table: one 16-byte load in float, two in
+// double
+template <typename T> struct ZRow {
+  T s2, ks, kz2;
+};
+__device__ __forceinline__ ZRow<float> zrow(const float* t, int mz) {
+  const float4 v = reinterpret_cast<const float4*>(t)[mz];
+  return {v.x, v.y, v.z};
+}
+__device__ __forceinline__ ZRow<double> zrow(const double* t, int mz) {
+  const double2 a = reinterpret_cast<const double2*>(t)[2 * mz];
+  const double b = t[4 * mz + 2];
+  return {a.x, a.y, b};
+}
+
 constexpr int kPassThreads = 256;
 
 // ------------------------------------------------------------------------------------------
@@ -341,9 +356,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   const double scale = br->scale;
   cplx<T>* W = static_cast<cplx<T>*>(br->W);
   cplx<T>* base = W + (size_t)p0 * nz;
-  const T* zs2 = static_cast<const T*>(br->zt[0]);
-  const T* zks = static_cast<const T*>(br->zt[1]);
-  const T* zkz2 = static_cast<const T*>(br->zt[2]);
+  const T* zt = static_cast<const T*>(br->zt);
 
   load_twiddles<T, M, NT>(tw, twg, tid);
   if (tid < PP) {
@@ -439,7 +452,8 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
         return (e < nz && p < nvalid && !(own0 && p == 0)) ? base[(size_t)p * nz + e] : mk<T>(T(0), T(0));
       },
       [&](int mz, int p, cplx<T>& v) {
-        const T s2 = zs2[mz], ks = zks[mz], kz2 = zkz2[mz];
+        const ZRow<T> zr = zrow(zt, mz);
+          const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
         T gk;
         if (sasha) {
           gk = (pzero[p] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[p] + kz2);

@@ -38,8 +38,8 @@ struct BoxRec {
   double* partials;
   int npartials;
   SashaCoef* coef;
-  const void* zt[3];     // 1 - cos(kz L), kz sin(kz L), kz^2 in the plan precision
-  const double* zt64[3]; // the same in double
+  const void* zt;        // rows {1 - cos(kz L), kz sin(kz L), kz^2, 0} per kz, plan precision
+  const double* zt64[3]; // the three columns separately in double
 };
 
 // A launch serves a group of boxes with the same kernel shape.

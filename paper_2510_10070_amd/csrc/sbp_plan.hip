@@ -539,10 +539,12 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
     if (!boxes) return fail(SBP_E_ARG, "boxes is NULL");
     if (nbox < 1 || nbox > 4096) return fail(SBP_E_ARG, "nbox=%d outside [1, 4096]", nbox);
     if (precision != SBP_FP64 && precision != SBP_FP32) return fail(SBP_E_ARG, "unknown precision %d", precision);
-    if (flags & ~(SBP_FLAG_GRAPH | SBP_FLAG_AUTOTUNE | SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS))
+    if (flags & ~(SBP_FLAG_GRAPH | SBP_FLAG_AUTOTUNE | SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS | SBP_FLAG_FUSED))
       return fail(SBP_E_ARG, "unknown flags 0x%x", flags);
-    if ((flags & SBP_FLAG_PLAIN) && (precision != SBP_FP64 || nbox != 1))
-      return fail(SBP_E_ARG, "the plain path is FP64 and single-box");
+    if ((flags & SBP_FLAG_FIVE_PASS) && (flags & SBP_FLAG_FUSED))
+      return fail(SBP_E_ARG, "SBP_FLAG_FIVE_PASS and SBP_FLAG_FUSED are exclusive");
+    if ((flags & SBP_FLAG_PLAIN) && (precision != SBP_FP64 || nbox != 1 || (flags & (SBP_FLAG_FIVE_PASS | SBP_FLAG_FUSED))))
+      return fail(SBP_E_ARG, "the plain path is FP64, single-box and takes no schedule flag");
     if (device < 0) return fail(SBP_E_ARG, "device=%d", device);
     const int prec = precision == SBP_FP32 ? 1 : 0;
     for (int i = 0; i < nbox; ++i) {
@@ -578,15 +580,16 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       bi.zt64[0] = put_vec<double>(tb, s2);
       bi.zt64[1] = put_vec<double>(tb, ks);
       bi.zt64[2] = put_vec<double>(tb, kz2);
-      if (prec) {
-        bi.zt[0] = put_vec<float>(tb, s2);
-        bi.zt[1] = put_vec<float>(tb, ks);
-        bi.zt[2] = put_vec<float>(tb, kz2);
-      } else {
-        for (int k = 0; k < 3; ++k) bi.zt[k] = bi.zt64[k];
+      std::vector<long double> rows(4 * s2.size(), 0.0L);
+      for (size_t i = 0; i < s2.size(); ++i) {
+        rows[4 * i] = s2[i];
+        rows[4 * i + 1] = ks[i];
+        rows[4 * i + 2] = kz2[i];
       }
+      bi.zt = prec ? put_vec<float>(tb, rows) : put_vec<double>(tb, rows);
       sbp::default_variants(prec, bi.g, bi.var);
-      bi.fused = !(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS)) && sbp::fused_ok(bi.g);
+      const bool want_fused = (flags & SBP_FLAG_FUSED) || (!(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS)) && prec == 1);
+      bi.fused = want_fused && sbp::fused_ok(bi.g);
       const size_t n = (size_t)b.nx * b.ny * b.nz;
       bi.data_bytes = n * w;
       if (flags & SBP_FLAG_PLAIN) {
@@ -643,10 +646,8 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       rec.partials = p->d_partials + bi.part_off;
       rec.npartials = 0;
       rec.coef = p->d_coef + b;
-      for (int k = 0; k < 3; ++k) {
-        rec.zt[k] = p->d_tables + bi.zt[k];
-        rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
-      }
+      rec.zt = p->d_tables + bi.zt;
+      for (int k = 0; k < 3; ++k) rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
     }
 
     p->nslots = 64;

@@ -95,6 +95,10 @@ def test_bad_plan_arguments():
     assert st == 1
     st, _ = _create([good()], prec=1, flags=_lib.SBP_FLAG_PLAIN)  # plain path is FP64 only
     assert st == 1
+    st, _ = _create([good()], prec=0, flags=_lib.SBP_FLAG_PLAIN | _lib.SBP_FLAG_FUSED)
+    assert st == 1
+    st, _ = _create([good()], flags=_lib.SBP_FLAG_FUSED | _lib.SBP_FLAG_FIVE_PASS)  # exclusive schedules
+    assert st == 1
     st, _ = _create([good()], nbox=0)
     assert st == 1
     h = ctypes.c_void_p()

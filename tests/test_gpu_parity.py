@@ -154,7 +154,8 @@ def test_batched_groups_and_autotune(precision, tmp_path, monkeypatch):
     # the five-pass kernels come in several tile variants (the autotuner times them; the second
     # autotuned plan reads the cache); the fused schedule has one tile shape per length
     for autotune, five in ((False, False), (True, True), (True, True), (True, False)):
-        got, used = gpu_solve(boxes, rhos, shears, precision, autotune=autotune, five_pass=five)
+        got, used = gpu_solve(boxes, rhos, shears, precision, autotune=autotune,
+                               schedule="five_pass" if five else "fused")
         for b, g, u, s in zip(boxes, got, used, shears):
             assert rel_l2(g, oracle_solve(b, u, s)) <= TOL[precision]
     assert (tmp_path / "tune.txt").exists()
@@ -200,10 +201,10 @@ def test_fused_schedule_parity(shape, method, precision):
     box = _box(shape, method)
     rho = lognormal_density(shape[:3], shape[5], 0.2 * shape[5], seed=sum(shape[:3]) + 101)
     shear = (1.5, 1.0, 0.83, 0.7)
-    got, used = gpu_solve(box, rho, shear, precision)
+    got, used = gpu_solve(box, rho, shear, precision, schedule="fused")
     ref = oracle_solve(box, used[0], shear)
     err = rel_l2(got[0], ref)
-    five, _ = gpu_solve(box, used[0], shear, precision, five_pass=True)
+    five, _ = gpu_solve(box, used[0], shear, precision, schedule="five_pass")
     err5 = rel_l2(five[0], ref)
     print(f"{shape} {method} {precision}: fused {err:.3e} five-pass {err5:.3e}")
     assert err <= TOL[precision], err
@@ -215,7 +216,7 @@ def test_fused_is_selected_and_mixed_schedules():
 
     for boxes, want in (([Box(32, 32, 32, 1.0, 1.0, 1.0)], "fused-3pass"),
                         ([Box(32, 32, 32, 1.0, 1.0, 1.0), Box(48, 32, 16, 1.0, 1.0, 1.0)], "mixed")):
-        plan = Plan(boxes, precision="fp32")
+        plan = Plan(boxes, precision="fp64", schedule="fused")
         d = plan.describe()
         plan.close()
         assert want in str(d), d
@@ -225,6 +226,6 @@ def test_fused_is_selected_and_mixed_schedules():
     rhos = [lognormal_density(s, 1.0, 0.2, seed=70 + i) for i, s in enumerate(shapes)]
     shears = [(1.5, 1.0, 0.1 + 0.4 * i, 1.0) for i in range(3)]
     for prec in ("fp64", "fp32"):
-        got, used = gpu_solve(boxes, rhos, shears, prec, graph=True)
+        got, used = gpu_solve(boxes, rhos, shears, prec, graph=True, schedule="fused")
         for b, g, u, s in zip(boxes, got, used, shears):
             assert rel_l2(g, oracle_solve(b, u, s)) <= TOL[prec]
