@@ -60,6 +60,33 @@ LEGS = (("fp32", "fp32", False, True), ("fp64", "fp64", False, True), ("plain_fp
         ("fp32_direct", "fp32", False, False), ("fp64_direct", "fp64", False, False))
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grf256_fp32.json")
+
+
+def kernel_source_digest(files) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, scaled by the plain-copy
+    calibration; None when no summary exists or the kernel's sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or kernel_source_digest(rec["sources"]) != rec["sources_sha256"]:
+        return None
+    return int(round((k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024))
+
+
 def copy_calibration(mib: int, steps: int) -> int:
     """A plain device-to-device copy of known size, for scaling hardware byte counters."""
     import torch
@@ -89,7 +116,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-samples", type=int, default=2)
+    ap.add_argument("--cpu-samples", type=int, default=2, help="minimum oracle solves")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample length")
     ap.add_argument("--only", choices=[leg[0] for leg in LEGS],
                     help="time one leg and print its kernel split (for profiler runs)")
     ap.add_argument("--schedule", choices=["auto", "fused", "five_pass"], default="auto",
@@ -161,8 +189,9 @@ def main() -> int:
         osh = oracle.Shear(q, om, t, G)
         times = []
         ref64 = None
-        for i in range(max(1, args.cpu_samples)):
-            log(f"oracle solve {i + 1} (FP64 input)")
+        # a bounded sample: whole solves until about cpu_seconds of work (at least cpu_samples)
+        while len(times) < max(1, args.cpu_samples) or sum(times) < args.cpu_seconds:
+            log(f"oracle solve {len(times) + 1} (FP64 input)")
             t0 = time.perf_counter()
             ref64 = oracle.solve(phis["fp64"][1], ob, osh)
             times.append(time.perf_counter() - t0)
@@ -173,8 +202,9 @@ def main() -> int:
         for leg, ref in (("fp32", ref32), ("fp64", ref64), ("plain_fp64", ref64)):
             errs[leg] = float(np.linalg.norm(phis[leg][0] - ref) / np.linalg.norm(ref))
         med = float(np.median(times))
-        cpu = {"value": 1.0 / med, "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(times)} full 256^3 FP64 oracle solves (numpy, single thread), median {med:.2f} s"}
+        cpu = {"value": round(1.0 / med, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(times)} full 256^3 FP64 oracle solves of the same input (numpy, one thread), "
+                         f"{sum(times):.1f} s in total, median {med:.2f} s per solve"}
 
     # roofline of the dominant kernel of the headline (FP32) leg
     k = res["fp32_direct"]["kernels"]
@@ -183,8 +213,8 @@ def main() -> int:
     per_launch_bytes = 2 * N * 4  # each pass reads and writes N*w bytes (rho/phi or the half spectrum)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
-            "avg_us": round(avg_ms * 1e3, 2)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
+            "avg_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": per_launch_bytes}
 
     head = res["fp32"]
     out = {
