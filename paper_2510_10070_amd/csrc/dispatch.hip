@@ -46,3 +46,40 @@ hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, 
 }
 
 }  // namespace sbp
+
+namespace sbp {
+
+// Per-solve records: the host writes them into a pinned ring slot and this kernel, the first of
+// every solve, copies the slot into the device record array.  Direct launches pass the slot;
+// a captured graph passes -1 and the kernel takes the slot from ctl[0], which the last block to
+// finish advances (ctl[1] counts finished blocks), so the replayed graph never changes.
+__global__ __launch_bounds__(256) void k_fetch(const BoxRec* __restrict__ ring, BoxRec* __restrict__ recs, int nrec,
+                                               int nslots, int slot_arg, int* ctl) {
+  const int slot = slot_arg >= 0 ? slot_arg : ctl[0];
+  constexpr int W = sizeof(BoxRec) / sizeof(uint2);
+  const size_t words = (size_t)nrec * W;
+  const uint2* src = reinterpret_cast<const uint2*>(ring + (size_t)slot * nrec);
+  uint2* dst = reinterpret_cast<uint2*>(recs);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+  if (slot_arg < 0) {
+    __syncthreads();  // every thread of this block has read the slot number
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(&ctl[1], 1) == (int)gridDim.x - 1) {
+        atomicExch(&ctl[1], 0);
+        atomicExch(&ctl[0], slot + 1 == nslots ? 0 : slot + 1);
+      }
+    }
+  }
+}
+static_assert(sizeof(BoxRec) % sizeof(uint2) == 0, "records are copied as 8-byte words");
+
+hipError_t launch_fetch(const BoxRec* ring, BoxRec* recs, int nrec, int nslots, int slot, int* ctl, hipStream_t st) {
+  const size_t words = (size_t)nrec * (sizeof(BoxRec) / sizeof(uint2));
+  const int blocks = (int)std::min<size_t>((words + 255) / 256, 256);
+  hipLaunchKernelGGL(k_fetch, dim3(blocks), dim3(256), 0, st, ring, recs, nrec, nslots, slot, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace sbp

@@ -46,12 +46,15 @@ template <typename T, int N, int V> constexpr int x_zc() {
   constexpr int big = sizeof(T) == 4 ? (N <= 512 ? 16 : 8) : (N <= 512 ? 8 : 4);
   return V ? big : big / 2;
 }
-// z: pencils per tile (variant 1 targets a 32 KiB padded tile, variant 0 half of that)
-template <typename T, int M, int V> constexpr int z_pp() {
-  constexpr int pp = 32768 / (M * 2 * (int)sizeof(T));
-  constexpr int big = pp < 1 ? 1 : (pp > 32 ? 32 : pp);
-  return V ? big : (big > 1 ? big / 2 : 1);
+// z: pencils one wavefront transforms side by side (about eight points per lane), pencils per
+// wavefront (variant 1: four such groups, variant 0: two; at most 64), pencils per block
+template <int M> constexpr int z_pw() { return M >= 512 ? 1 : 512 / M; }
+template <int M, int V> constexpr int z_ppw() {
+  constexpr int k = V ? 4 : 2;
+  constexpr int cap = 64 / z_pw<M>() < 1 ? 1 : 64 / z_pw<M>();
+  return z_pw<M>() * (k < cap ? k : cap);
 }
+template <typename T, int M, int V> constexpr int z_pp() { return (kPassThreads / 64) * z_ppw<M, V>(); }
 
 // ------------------------------------------------------------------------------------------
 // launch groups
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   const int hy = NY / 2;
   const T* rho = static_cast<const T*>(br->rho);
   cplx<T>* W = static_cast<cplx<T>*>(br->W);
-  double* partials = REMAP ? br->partials : nullptr;
+  double* partials = (REMAP && g.method == 1) ? br->partials : nullptr;  // SASHA sums only
 
   load_twiddles<T, NY, NT>(tw, twg, tid);
   if (REMAP) {
@@ -316,11 +319,13 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
 }
 
 // ------------------------------------------------------------------------------------------
-// z: one block per PP consecutive (Kx, Ky) pencils (contiguous in W).  Each pencil is padded
-// to M = Q*Nz (Hockney; never stored), transformed, multiplied by the Green's function at
-// k = |(Kx + s Ky, Ky)| (Sect. 2.1) times 4 pi G/(Nx Ny M), transformed back; its first Nz
-// values are stored in place.  The forward output feeds the inverse in registers; the zero
-// half of the input and the discarded half of the output are dropped at compile time.
+// z: one block per 4 * PPW consecutive (Kx, Ky) pencils (contiguous in W); each wavefront owns
+// PPW of them and runs them PW at a time (eight points per lane) through its private LDS
+// exchange tile, with no workgroup barrier.  Each pencil is padded to M = Q*Nz (Hockney; never
+// stored), transformed, multiplied by the Green's function at k = |(Kx + s Ky, Ky)| (Sect. 2.1)
+// times 4 pi G/(Nx Ny M), transformed back; its first Nz values are stored in place.  The
+// forward output feeds the inverse in registers; the zero half of the input and the discarded
+// half of the output are dropped at compile time.
 //
 // Green's function (Sect. 2.3, App. A), L = alpha Lz, E = exp(-kL):
 //   VGF, k > 0:  -((1 - E) + E (1 - cos(kz L)) + E (kz/k) sin(kz L)) / (k^2 + kz^2)
@@ -334,33 +339,39 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
 template <typename T, int M, int V, int Q>
 __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                     const cplx<T>* __restrict__ twg, const double2* __restrict__ tw64) {
-  constexpr int PP = z_pp<T, M, V>();
+  constexpr int PW = z_pw<M>();
+  constexpr int PPW = z_ppw<M, V>();
+  constexpr int WV = kPassThreads / 64;
   constexpr int NT = kPassThreads;
   constexpr bool kF32 = std::is_same<T, float>::value;
-  using L = Tile<PP, 1, M, false>;
-  __shared__ cplx<T> buf[lds_slots(PP * M)];
+  using LW = Tile<PW, 1, M, false>;
+  constexpr int XS = lds_slots(PW * M);
+  __shared__ cplx<T> xbuf[WV * XS];
   __shared__ cplx<T> tw[M];
-  __shared__ T pa0[PP], pe[PP], pik[PP], pk2[PP];
-  __shared__ int pzero[PP];
+  __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW];
+  __shared__ int pzero[WV][PPW];
+  // block-0 work before the wavefront transforms borrows xbuf (SASHA reduction, then the double
+  // k = 0 exchange tile of float plans)
+  static_assert(lds_slots(M) * 16 <= WV * XS * (int)sizeof(cplx<T>), "k = 0 tile must fit");
+  static_assert(2 * NT * 8 <= WV * XS * (int)sizeof(cplx<T>), "reduction scratch must fit");
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int hy = g.ny / 2;
   const int np = g.nx * hy;
-  const int p0 = t * PP;
   const int nz = g.nz;
-  const int nvalid = min(PP, np - p0);
   const bool sasha = g.method == 1;
   const double scale = br->scale;
   cplx<T>* W = static_cast<cplx<T>*>(br->W);
-  cplx<T>* base = W + (size_t)p0 * nz;
   const T* zt = static_cast<const T*>(br->zt);
+  const int pw0 = (t * WV + wave) * PPW;  // first pencil of this wavefront
 
   load_twiddles<T, M, NT>(tw, twg, tid);
-  if (tid < PP) {
-    const int q = p0 + tid;
+  if (lane < PPW) {
+    const int q = min(pw0 + lane, np - 1);
     const int mx = q / hy, my = q - mx * hy;
     const int sx = mx < g.nx / 2 ? mx : mx - g.nx;
     const double two_pi = 6.283185307179586476925286766559;
@@ -369,39 +380,39 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
     const double k2 = kx * kx + Ky * Ky;
     const double k = sqrt(k2);
     const int zero = (mx == 0 && my == 0);
-    pzero[tid] = zero;
-    pk2[tid] = (T)k2;
+    pzero[wave][lane] = zero;
+    pk2[wave][lane] = (T)k2;
     if (!zero && !sasha) {
-      pa0[tid] = (T)(-expm1(-k * g.L) * scale);
-      pe[tid] = (T)(exp(-k * g.L) * scale);
-      pik[tid] = (T)(1.0 / k);
+      pa0[wave][lane] = (T)(-expm1(-k * g.L) * scale);
+      pe[wave][lane] = (T)(exp(-k * g.L) * scale);
+      pik[wave][lane] = (T)(1.0 / k);
     } else {
-      pa0[tid] = T(0);
-      pe[tid] = T(0);
-      pik[tid] = T(0);
+      pa0[wave][lane] = T(0);
+      pe[wave][lane] = T(0);
+      pik[wave][lane] = T(0);
     }
   }
 
   // SASHA: <rho> and the centre of mass from the y-pass partial sums (fixed order)
   if (sasha && t == 0) {
-    __shared__ double red[2][NT];
+    double* red = reinterpret_cast<double*>(xbuf);
     double a = 0.0, b = 0.0;
     for (int i = tid; i < br->npartials; i += NT) {
       a += br->partials[2 * i];
       b += br->partials[2 * i + 1];
     }
-    red[0][tid] = a;
-    red[1][tid] = b;
+    red[tid] = a;
+    red[NT + tid] = b;
     __syncthreads();
     for (int o = NT / 2; o > 0; o >>= 1) {
       if (tid < o) {
-        red[0][tid] += red[0][tid + o];
-        red[1][tid] += red[1][tid + o];
+        red[tid] += red[tid + o];
+        red[NT + tid] += red[NT + tid + o];
       }
       __syncthreads();
     }
     if (tid == 0) {
-      const double s0 = red[0][0], s1 = red[1][0];
+      const double s0 = red[0], s1 = red[NT];
       SashaCoef c;
       c.c2 = 0.0;
       c.c1 = 0.0;
@@ -413,13 +424,14 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
       *br->coef = c;
     }
   }
+  __syncthreads();  // twiddles loaded; reduction scratch free
 
-  // float plans: the k = 0 pencil (pencil 0 of tile 0) in double, using the exchange tile
+  // float plans: the k = 0 pencil (pencil 0 of tile 0) in double, block-wide
   const bool own0 = kF32 && t == 0;
   if constexpr (kF32) {
     if (t == 0) {
       using L1 = Tile<1, 1, M, false>;
-      double2* dbuf = reinterpret_cast<double2*>(buf);
+      double2* dbuf = reinterpret_cast<double2*>(xbuf);
       float2* w0 = reinterpret_cast<float2*>(W);
       const double* z64s2 = br->zt64[0];
       const double* z64ks = br->zt64[1];
@@ -440,34 +452,43 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
           [&](int e, int, double2 v) {
             if (e < nz) w0[e] = make_float2((float)v.x, (float)v.y);
           });
+      __syncthreads();  // xbuf is handed to the wavefronts
     }
   }
-  __syncthreads();
 
   const T L_ = (T)g.L;
   const T sc = (T)scale;
-  fft_fwd_op_inv<T, M, L, NT, 0, Q>(
-      buf, tw, tid,
-      [&](int e, int p) {
-        return (e < nz && p < nvalid && !(own0 && p == 0)) ? base[(size_t)p * nz + e] : mk<T>(T(0), T(0));
-      },
-      [&](int mz, int p, cplx<T>& v) {
-        const ZRow<T> zr = zrow(zt, mz);
+  cplx<T>* xw = xbuf + wave * XS;
+#pragma unroll 1
+  for (int g0 = 0; g0 < PPW; g0 += PW) {
+    if (pw0 + g0 >= np) break;  // uniform across the wavefront
+    fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
+        xw, tw, lane,
+        [&](int e, int p) {
+          const int q = pw0 + g0 + p;
+          return (e < nz && q < np && !(own0 && q == 0)) ? W[(size_t)q * nz + e] : mk<T>(T(0), T(0));
+        },
+        [&](int mz, int p, cplx<T>& v) {
+          const int i = g0 + p;
+          const ZRow<T> zr = zrow(zt, mz);
           const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
-        T gk;
-        if (sasha) {
-          gk = (pzero[p] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[p] + kz2);
-        } else if (!pzero[p]) {
-          gk = -(pa0[p] + pe[p] * (s2 + pik[p] * ks)) * fast_rcp(pk2[p] + kz2);
-        } else {
-          gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
-        }
-        v.x *= gk;
-        v.y *= gk;
-      },
-      [&](int e, int p, cplx<T> v) {
-        if (e < nz && p < nvalid && !(own0 && p == 0)) base[(size_t)p * nz + e] = v;
-      });
+          T gk;
+          if (sasha) {
+            gk = (pzero[wave][i] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[wave][i] + kz2);
+          } else if (!pzero[wave][i]) {
+            gk = -(pa0[wave][i] + pe[wave][i] * (s2 + pik[wave][i] * ks)) * fast_rcp(pk2[wave][i] + kz2);
+          } else {
+            gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
+          }
+          v.x *= gk;
+          v.y *= gk;
+        },
+        [&](int e, int p, cplx<T> v) {
+          const int q = pw0 + g0 + p;
+          if (e < nz && q < np && !(own0 && q == 0)) W[(size_t)q * nz + e] = v;
+        });
+    WaveSync::sync();  // the exchange tile is rewritten by the next pencils of this wavefront
+  }
 }
 
 // ------------------------------------------------------------------------------------------

@@ -83,6 +83,10 @@ int fused_a(const BoxGeom& g);
 hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
 
+// Copy the records of one solve from pinned ring slot `slot` (or, with slot < 0, from the slot
+// named by ctl[0], which the kernel then advances) into the device record array.
+hipError_t launch_fetch(const BoxRec* ring, BoxRec* recs, int nrec, int nslots, int slot, int* ctl, hipStream_t st);
+
 // Plain (unfused) FP64 path for one box: rec0 views the half spectrum, rec_pad the padded one.
 constexpr int kPlainPartials = 1024;
 hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* d_rec0, const BoxRec* d_rec_pad, GroupArgs one,

@@ -79,8 +79,10 @@ struct sbp_plan_s {
   size_t ws_need = 0;
   char* ws = nullptr;
   bool ws_owned = false;
-  // pinned staging ring for the per-solve records
+  // pinned staging ring for the per-solve records (h_stage: host view, d_stage: device view)
   sbp::BoxRec* h_stage = nullptr;
+  const sbp::BoxRec* d_stage = nullptr;
+  int* d_ctl = nullptr;  // graph mode: {next ring slot, finished fetch blocks}
   int nslots = 0, slot = 0;
   size_t nrec = 0;  // records per solve
   std::vector<hipEvent_t> slot_ev;
@@ -323,9 +325,12 @@ hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
   }
 }
 
-// launch one solve (records already on the device)
-sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk) {
+// launch one solve: the record fetch, then the passes.  fetch_slot < 0: the slot comes from the
+// device-side ring counter (graph capture).
+sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot) {
   const char* T = p->d_tables;
+  if (mk) mk->mark("records");
+  HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
   if (p->flags & SBP_FLAG_PLAIN) {
     const BoxInfo& bi = p->boxes[0];
     sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1};
@@ -364,11 +369,10 @@ void bind_workspace(sbp_plan p) {
   for (size_t b = 0; b < p->boxes.size(); ++b) p->master[b].W = p->ws + p->boxes[b].ws_off;
 }
 
-// fill a staging slot with the records of one solve and copy it to the device
-sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params,
-                         hipStream_t st) {
+// fill the next ring slot with the records of one solve (the fetch kernel copies it to the
+// device); waits only if that slot's previous solve has not yet been fetched
+sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, int* slot_out) {
   const int slot = p->slot;
-  p->slot = (p->slot + 1) % p->nslots;
   if (p->slot_used[slot]) HIP_TRY(hipEventSynchronize(p->slot_ev[slot]));
   sbp::BoxRec* hs = p->h_stage + (size_t)slot * p->nrec;
   for (size_t r = 0; r < p->nrec; ++r) {
@@ -386,7 +390,13 @@ sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, c
     hs[r].fourpiG = 4.0 * M_PI * s.G;
     hs[r].scale = hs[r].fourpiG / ((double)g.nx * g.ny * g.m);
   }
-  HIP_TRY(hipMemcpyAsync(p->d_recs, hs, p->nrec * sizeof(sbp::BoxRec), hipMemcpyHostToDevice, st));
+  *slot_out = slot;
+  return SBP_OK;
+}
+
+// after the solve using `slot` is enqueued: advance the ring and mark the slot in flight
+sbp_status commit_slot(sbp_plan p, int slot, hipStream_t st) {
+  p->slot = (slot + 1) % p->nslots;
   HIP_TRY(hipEventRecord(p->slot_ev[slot], st));
   p->slot_used[slot] = true;
   return SBP_OK;
@@ -479,7 +489,15 @@ sbp_status plan_time_groups(sbp_plan p, int reps, std::vector<Launch>& launches,
   std::vector<hipEvent_t> ev(p->launches.size() + 1);
   for (auto& e : ev) hipEventCreate(&e);
   for (int r = 0; r <= reps && res == SBP_OK; ++r) {
-    res = stage_records(p, rho.data(), phi.data(), sh.data(), st);
+    int slot = 0;
+    res = stage_records(p, rho.data(), phi.data(), sh.data(), &slot);
+    if (res != SBP_OK) break;
+    if (hipError_t e = sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, slot, p->d_ctl, st);
+        e != hipSuccess) {
+      res = fail(SBP_E_HIP, "autotune record fetch: %s", hipGetErrorString(e));
+      break;
+    }
+    res = commit_slot(p, slot, st);
     if (res != SBP_OK) break;
     hipEventRecord(ev[0], st);
     for (size_t i = 0; i < p->launches.size(); ++i) {
@@ -622,11 +640,18 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
     // group ints: per pass at most nbox groups; each box appears once per pass with 2 ints,
     // plus one leading start per group
     p->nints_cap = 8 * (3 * (size_t)nbox) + 8;
-    const size_t aux = align_up(p->nrec * sizeof(sbp::BoxRec)) + align_up(nbox * sizeof(sbp::SashaCoef)) +
+    const size_t aux = align_up(2 * sizeof(int)) + align_up(p->nrec * sizeof(sbp::BoxRec)) +
+                       align_up(nbox * sizeof(sbp::SashaCoef)) +
                        align_up(std::max<size_t>(npart, 2) * sizeof(double)) + align_up(p->nints_cap * sizeof(int));
     if (hipMalloc(&d, aux) != hipSuccess) return fail(SBP_E_NOMEM, "aux allocation (%zu bytes)", aux);
     p->d_aux = (char*)d;
     char* cur = p->d_aux;
+    p->d_ctl = (int*)cur;
+    cur += align_up(2 * sizeof(int));
+    {
+      const int zero[2] = {0, 0};
+      HIP_TRY(hipMemcpy(p->d_ctl, zero, sizeof zero, hipMemcpyHostToDevice));
+    }
     p->d_recs = (sbp::BoxRec*)cur;
     cur += align_up(p->nrec * sizeof(sbp::BoxRec));
     p->d_coef = (sbp::SashaCoef*)cur;
@@ -655,6 +680,9 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
     if (hipHostMalloc(&h, (size_t)p->nslots * p->nrec * sizeof(sbp::BoxRec), hipHostMallocDefault) != hipSuccess)
       return fail(SBP_E_NOMEM, "pinned staging allocation");
     p->h_stage = (sbp::BoxRec*)h;
+    void* dv = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&dv, h, 0));
+    p->d_stage = (const sbp::BoxRec*)dv;
     p->slot_ev.resize(p->nslots);
     p->slot_used.assign(p->nslots, false);
     for (auto& e : p->slot_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -750,7 +778,17 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
         return fail(SBP_E_ARG, "rho or phi of box %zu overlaps the workspace", b);
     bind_workspace(p);
     hipStream_t st = (hipStream_t)stream;
-    sbp_status ss = stage_records(p, rho, phi, params, st);
+    if ((p->flags & SBP_FLAG_GRAPH) && !p->gexec) {
+      // the replayed fetch kernel follows the device-side ring counter: start it and the host
+      // ring at slot 0, once every earlier (direct, e.g. autotuning) use of the ring is done
+      for (int i = 0; i < p->nslots; ++i)
+        if (p->slot_used[i]) HIP_TRY(hipEventSynchronize(p->slot_ev[i]));
+      const int zero[2] = {0, 0};
+      HIP_TRY(hipMemcpy(p->d_ctl, zero, sizeof zero, hipMemcpyHostToDevice));
+      p->slot = 0;
+    }
+    int slot = 0;
+    sbp_status ss = stage_records(p, rho, phi, params, &slot);
     if (ss != SBP_OK) return ss;
 
     if (p->flags & SBP_FLAG_GRAPH) {
@@ -758,7 +796,7 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
         // the launches read everything per-solve from the device records: capture once
         if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        sbp_status es = enqueue(p, p->cap_stream, nullptr);
+        sbp_status es = enqueue(p, p->cap_stream, nullptr, -1);
         hipGraph_t gr = nullptr;
         hipError_t ce = hipStreamEndCapture(p->cap_stream, &gr);
         if (es != SBP_OK) {
@@ -769,14 +807,17 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
         p->graph = gr;
         HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
       }
+      // the replay fetches ring slot ctl[0], which advances in step with p->slot
       Marker mk{p, st};
       if (p->prof) mk.mark("graph");
       HIP_TRY(hipGraphLaunch(p->gexec, st));
       if (p->prof) mk.mark(nullptr);
-      return SBP_OK;
+      return commit_slot(p, slot, st);
     }
     Marker mk{p, st};
-    return enqueue(p, st, p->prof ? &mk : nullptr);
+    sbp_status es = enqueue(p, st, p->prof ? &mk : nullptr, slot);
+    if (es != SBP_OK) return es;
+    return commit_slot(p, slot, st);
   } catch (const std::bad_alloc&) {
     return fail(SBP_E_NOMEM, "host allocation failed");
   } catch (...) {
