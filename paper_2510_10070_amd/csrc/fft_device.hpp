@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace sbp {
 
 template <typename T> struct cvec;
@@ -246,7 +248,13 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
       int j, b;
       if (item(tid, p, j, b)) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[p][r] = r < RIN ? f(j + r * NBF, b) : mk<T>(T(0), T(0));
+        for (int r = 0; r < R; ++r) {
+          // a functor taking a third argument also gets the register slot p R + r
+          if constexpr (std::is_invocable_v<F&, int, int, int>)
+            v[p][r] = r < RIN ? f(j + r * NBF, b, p * R + r) : mk<T>(T(0), T(0));
+          else
+            v[p][r] = r < RIN ? f(j + r * NBF, b) : mk<T>(T(0), T(0));
+        }
       }
     }
   }
@@ -296,7 +304,12 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
         const int k = j % NS;
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < ROUT; ++r) f(base + r * NS, b, v[p][r]);
+        for (int r = 0; r < ROUT; ++r) {
+          if constexpr (std::is_invocable_v<F&, int, int, cplx<T>, int>)
+            f(base + r * NS, b, v[p][r], p * R + r);
+          else
+            f(base + r * NS, b, v[p][r]);
+        }
       }
     }
   }

@@ -320,43 +320,50 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
 
 // ------------------------------------------------------------------------------------------
 // Pass B: one block per (k1, my).  The B-point DFT across the j pencils runs in registers
-// (each thread owns z positions) and parks the B pencils in LDS.  Then every wavefront takes
-// whole pencils: the padded z transform, the Green multiply for Kx = k1 + A k2 and the inverse
-// run in its registers and a wavefront-private LDS exchange tile, with no workgroup barrier.
-// A final barrier, and the inverse B-point DFT goes back to HBM.
+// (one thread per z) and parks the B pencils in the LDS tile.  Every wavefront then takes
+// pairs of pencil groups (PW pencils each): it lifts the inputs of both groups into registers,
+// uses the tile area of the pair as its exchange buffer for the padded z transform, the Green
+// multiply for Kx = k1 + A k2 and the inverse of each group in turn, and writes both results
+// back; no workgroup barrier and no LDS beyond the tile.  A final barrier, and the inverse
+// B-point DFT goes back to HBM.  Float plans take the k = 0 pencil (tile 0, pencil 0) in
+// double as a direct convolution with the time-independent real-space kernel h.
 
-// pencils one wavefront transforms side by side (8 points per lane) and wavefronts per block
-template <int M> constexpr int fb_pw() { return M >= 512 ? 1 : 512 / M; }
-template <int M, int B> constexpr int fb_waves() {
-  constexpr int w = M >= 512 ? 8 : 4;  // 512: two blocks of eight wavefronts fit the 160 KB LDS
-  return B / fb_pw<M>() < w ? B / fb_pw<M>() : w;
+// pencils per transform (about eight points per lane; Q such groups share one tile area, whose
+// Q * PW * Nz slots are exactly one group's padded exchange buffer) and wavefronts per block
+template <int M, int B, int Q> constexpr int fb_pw() {
+  constexpr int a = M >= 512 ? 1 : 512 / M;
+  return a < B / Q ? a : B / Q;
 }
-template <int M, int B> constexpr int fb_threads() { return 64 * fb_waves<M, B>(); }
+template <int M, int B, int Q> constexpr int fb_tuples() { return B / (Q * fb_pw<M, B, Q>()); }
+template <int M, int B, int Q> constexpr int fb_waves() { return fb_tuples<M, B, Q>() < 4 ? fb_tuples<M, B, Q>() : 4; }
+template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves<M, B, Q>(); }
 
 template <typename T, int M, int B, int Q>
-__global__ __launch_bounds__(512) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
+__global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
                                             const cplx<T>* __restrict__ twm, const double2* __restrict__ twm64,
                                             int A) {
-  constexpr int PW = fb_pw<M>();
-  constexpr int WV = fb_waves<M, B>();
+  (void)twm64;
+  constexpr int PW = fb_pw<M, B, Q>();
+  constexpr int NTUP = fb_tuples<M, B, Q>();
+  constexpr int WV = fb_waves<M, B, Q>();
   constexpr int NT = 64 * WV;
   constexpr int NZ = M / Q;
+  constexpr int ZPT = (NZ + NT - 1) / NT;  // z columns per thread in the j transforms
   constexpr bool kF32 = std::is_same<T, float>::value;
+  static_assert(Q * PW * NTUP == B, "groups must tile the B pencils");
   using LT = Tile<B, 1, NZ, false>;  // parked pencils: element z of pencil k2
-  using LW = Tile<PW, 1, M, false>;  // one wavefront's exchange tile
-  constexpr int XS = lds_slots(PW * M);
+  using LW = Tile<PW, 1, M, false>;  // one group's exchange layout inside its tuple's tile area
+  using RF = typename Fwd<M>::L;
+  using RI = typename Inv<M>::L;
+  using S0 = Stage<T, M, RF, 0, LW, 64, -1>;
+  using SL = Stage<T, M, RI, RI::n - 1, LW, 64, +1>;
+  constexpr int RIN = (S0::R % Q == 0) ? S0::R / Q : S0::R;
+  constexpr int ROUT = (SL::R % Q == 0) ? SL::R / Q : SL::R;
   __shared__ cplx<T> tile[lds_slots(B * NZ)];
-  __shared__ cplx<T> xbuf[WV * XS];
   __shared__ cplx<T> tw[M];
   __shared__ T pa0[B], pe[B], pik[B], pk2[B];
   __shared__ int pzero[B];
-  // block-0 work before the wavefront transforms borrows xbuf: the double k = 0 exchange
-  // tile, the k = 0 pencil input in double and the SASHA reduction
-  constexpr int X64 = lds_slots(M);
-  static_assert((X64 + NZ) * 16 + 2 * NT * 8 <= WV * XS * (int)sizeof(cplx<T>), "block-0 scratch must fit");
-  double2* dbuf = reinterpret_cast<double2*>(xbuf);
-  double2* d0 = dbuf + X64;
-  double* red = reinterpret_cast<double*>(d0 + NZ);
+  __shared__ double d0[kF32 ? NZ : 1];  // float plans: real k = 0 pencil input in double
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -393,126 +400,132 @@ __global__ __launch_bounds__(512) void k_fb(GroupArgs ga, const BoxRec* __restri
     }
   }
 
-  // B-point DFT across j for each z
-  for (int z = tid; z < NZ; z += NT) {
-    cplx<T> v[B];
-#pragma unroll
-    for (int jj = 0; jj < B; ++jj) v[jj] = base[(size_t)jj * NZ + z];
-    if (own0) {
-      double sx = 0.0, sy = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < B; ++jj) {
-        sx += (double)v[jj].x;
-        sy += (double)v[jj].y;
-      }
-      d0[z] = make_double2(sx, sy);
-    }
-    Dft<B, -1, T>::run(v);
-#pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) tile[LT::at(z, k2)] = v[k2];
-  }
-
-  // SASHA: <rho> and the centre of mass from the pass-A partial sums (fixed order)
-  if (sasha && t == 0) {
+  // SASHA: <rho> and the centre of mass from the pass-A partial sums (first wavefront of the
+  // box's first block, fixed order)
+  if (sasha && t == 0 && tid < 64) {
     double a = 0.0, b = 0.0;
-    for (int i = tid; i < br->npartials; i += NT) {
+    for (int i = tid; i < br->npartials; i += 64) {
       a += br->partials[2 * i];
       b += br->partials[2 * i + 1];
     }
-    red[tid] = a;
-    red[NT + tid] = b;
-    __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-      if (tid < o) {
-        red[tid] += red[tid + o];
-        red[NT + tid] += red[NT + tid + o];
-      }
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      b += __shfl_xor(b, o);
     }
     if (tid == 0) {
-      const double s0 = red[0], s1 = red[NT];
       SashaCoef c;
       c.c2 = 0.0;
       c.c1 = 0.0;
-      if (s0 != 0.0) {
-        const double mean = s0 / ((double)g.nx * g.ny * g.m);
+      if (a != 0.0) {
+        const double mean = a / ((double)g.nx * g.ny * g.m);
         c.c2 = 0.5 * br->fourpiG * mean;
-        c.c1 = -br->fourpiG * mean * (s1 / s0);
+        c.c1 = -br->fourpiG * mean * (b / a);
       }
       *br->coef = c;
     }
   }
-  __syncthreads();
 
-  // float plans: the k = 0 pencil in double (block-wide), result parked in the tile
-  if constexpr (kF32) {
-    if (t == 0) {
-      using L1 = Tile<1, 1, M, false>;
-      const double* z64s2 = br->zt64[0];
-      const double* z64ks = br->zt64[1];
-      const double* z64kz2 = br->zt64[2];
-      fft_fwd_op_inv<double, M, L1, NT, 0, Q>(
-          dbuf, twm64, tid, [&](int e, int) { return e < NZ ? d0[e] : make_double2(0.0, 0.0); },
-          [&](int mz, int, double2& v) {
-            double gk;
-            if (sasha)
-              gk = mz == 0 ? 0.0 : -1.0 / z64kz2[mz];
-            else
-              gk = mz == 0 ? 0.5 * g.L * g.L : (g.L * z64ks[mz] - z64s2[mz]) / z64kz2[mz];
-            gk *= scale;
-            v.x *= gk;
-            v.y *= gk;
-          },
-          [&](int e, int, double2 v) {
-            if (e < NZ) tile[LT::at(e, 0)] = make_float2((float)v.x, (float)v.y);
-          });
-      __syncthreads();  // xbuf is handed to the wavefronts
+  // B-point DFT across j for each z
+#pragma unroll
+  for (int zi = 0; zi < ZPT; ++zi) {
+    const int z = tid + zi * NT;
+    if (NZ % NT == 0 || z < NZ) {
+      cplx<T> v[B];
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) v[jj] = base[(size_t)jj * NZ + z];
+      if (own0) {
+        double sx = 0.0;  // the k = 0 pencil is real: its imaginary parts are exact zeros
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj) sx += (double)v[jj].x;
+        d0[kF32 ? z : 0] = sx;
+      }
+      Dft<B, -1, T>::run(v);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) tile[LT::at(z, k2)] = v[k2];
     }
   }
+  __syncthreads();
 
-  // wavefront-private padded z transforms, Green multiply and inverse
+  // wavefront-private padded z transforms, Green multiply and inverse: Q groups per tile area
   const T* zt = static_cast<const T*>(br->zt);
   const T L_ = (T)g.L;
   const T sc = (T)scale;
   const int wave = tid >> 6, lane = tid & 63;
-  cplx<T>* xw = xbuf + wave * XS;
 #pragma unroll 1
-  for (int p0 = wave * PW; p0 < B; p0 += WV * PW) {
-    fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-        xw, tw, lane,
-        [&](int e, int p) {
-          return (e < NZ && !(own0 && p0 + p == 0)) ? tile[LT::at(e, p0 + p)] : mk<T>(T(0), T(0));
-        },
-        [&](int mz, int p, cplx<T>& v) {
-          const int k2 = p0 + p;
-          const ZRow<T> zr = zrow(zt, mz);
-          const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
-          T gk;
-          if (sasha) {
-            gk = (pzero[k2] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[k2] + kz2);
-          } else if (!pzero[k2]) {
-            gk = -(pa0[k2] + pe[k2] * (s2 + pik[k2] * ks)) * fast_rcp(pk2[k2] + kz2);
-          } else {
-            gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
-          }
-          v.x *= gk;
-          v.y *= gk;
-        },
-        [&](int e, int p, cplx<T> v) {
-          if (e < NZ && !(own0 && p0 + p == 0)) tile[LT::at(e, p0 + p)] = v;
-        });
-    WaveSync::sync();  // the exchange tile is rewritten by this wavefront's next pencils
+  for (int tu = wave; tu < NTUP; tu += WV) {
+    const int k0 = Q * PW * tu;  // first pencil of the tuple
+    cplx<T>* area = tile + pad8(k0 * NZ);  // Q * PW * NZ = PW * M logical slots
+    auto skip = [&](int k2) { return own0 && k2 == 0; };
+    cplx<T> in[Q][S0::PER][S0::R];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      S0::template read_fn<RIN>(in[q], lane, [&](int e, int p) {
+        const int k2 = k0 + q * PW + p;
+        return (e < NZ && !skip(k2)) ? tile[LT::at(e, k2)] : mk<T>(T(0), T(0));
+      });
+    WaveSync::sync();  // the area is free once every lane holds its inputs
+    cplx<T> out[Q][SL::PER][SL::R];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      __builtin_amdgcn_sched_barrier(0);  // one transform at a time (register pressure)
+      const int kq = k0 + q * PW;
+      fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
+          area, tw, lane, [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
+          [&](int mz, int p, cplx<T>& v) {
+            const int k2 = kq + p;
+            const ZRow<T> zr = zrow(zt, mz);
+            const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
+            T gk;
+            if (sasha) {
+              gk = (pzero[k2] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[k2] + kz2);
+            } else if (!pzero[k2]) {
+              gk = -(pa0[k2] + pe[k2] * (s2 + pik[k2] * ks)) * fast_rcp(pk2[k2] + kz2);
+            } else {
+              gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
+            }
+            v.x *= gk;
+            v.y *= gk;
+          },
+          [&](int, int, cplx<T> v, int i) { out[q][i / SL::R][i % SL::R] = v; });
+      WaveSync::sync();
+    }
+    // the exchange reads are done: the results go back into the area
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      SL::template write_fn<ROUT>(out[q], lane, [&](int e, int p, cplx<T> v) {
+        const int k2 = k0 + q * PW + p;
+        if (e < NZ && !skip(k2)) tile[LT::at(e, k2)] = v;
+      });
+    WaveSync::sync();  // this wavefront's next tuple starts from fresh reads
   }
   __syncthreads();
 
   // inverse B-point DFT across k2, store
-  for (int z = tid; z < NZ; z += NT) {
-    cplx<T> v[B];
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) v[k2] = tile[LT::at(z, k2)];
-    Dft<B, +1, T>::run(v);
+  for (int zi = 0; zi < ZPT; ++zi) {
+    const int z = tid + zi * NT;
+    if (NZ % NT == 0 || z < NZ) {
+      cplx<T> v[B];
 #pragma unroll
-    for (int jj = 0; jj < B; ++jj) base[(size_t)jj * NZ + z] = v[jj];
+      for (int k2 = 0; k2 < B; ++k2) v[k2] = tile[LT::at(z, k2)];
+      if constexpr (kF32) {
+        if (own0) {
+          // the k = 0 pencil in double: the padded circular convolution
+          // phi_0[z] = scale sum_z' h[(z - z') mod M] d0[z']
+          const double* h = br->k0h;
+          double acc = 0.0;
+#pragma unroll 2
+          for (int zp = 0; zp < NZ; ++zp) {
+            const int d = z - zp;
+            acc += h[d < 0 ? d + M : d] * d0[zp];
+          }
+          v[0] = mk<T>((T)(acc * scale), T(0));
+        }
+      }
+      Dft<B, +1, T>::run(v);
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) base[(size_t)jj * NZ + z] = v[jj];
+    }
   }
 }
 

@@ -40,6 +40,7 @@ struct BoxRec {
   SashaCoef* coef;
   const void* zt;        // rows {1 - cos(kz L), kz sin(kz L), kz^2, 0} per kz, plan precision
   const double* zt64[3]; // the three columns separately in double
+  const double* k0h;     // k = 0 pencil in real space: h[n] = sum_m G(0, kz_m) cos(2 pi m n/M)
 };
 
 // A launch serves a group of boxes with the same kernel shape.

@@ -605,6 +605,27 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
         rows[4 * i + 2] = kz2[i];
       }
       bi.zt = prec ? put_vec<float>(tb, rows) : put_vec<double>(tb, rows);
+      {
+        // the k = 0 Green's function does not depend on t: its real-space form on the padded
+        // grid, h[n] = sum_m G(0, kz_m) cos(2 pi m n / M), turns the k = 0 pencil into a short
+        // convolution (float plans evaluate it in double)
+        const int M = bi.g.m;
+        const long double L = (long double)bi.g.L;
+        std::vector<long double> gk(M), h(M, 0.0L);
+        for (int m = 0; m < M; ++m) {
+          if (b.method == SBP_SASHA)
+            gk[m] = m == 0 ? 0.0L : -1.0L / kz2[m];
+          else
+            gk[m] = m == 0 ? 0.5L * L * L : (L * ks[m] - s2[m]) / kz2[m];
+        }
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        for (int n = 0; n < M; ++n) {
+          long double acc = 0.0L;
+          for (int m = 0; m < M; ++m) acc += gk[m] * cosl(two_pi * (long double)(((long long)m * n) % M) / M);
+          h[n] = acc;
+        }
+        bi.k0h = put_vec<double>(tb, h);
+      }
       sbp::default_variants(prec, bi.g, bi.var);
       const bool want_fused = (flags & SBP_FLAG_FUSED) || (!(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS)) && prec == 1);
       bi.fused = want_fused && sbp::fused_ok(bi.g);
@@ -672,6 +693,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       rec.npartials = 0;
       rec.coef = p->d_coef + b;
       rec.zt = p->d_tables + bi.zt;
+      rec.k0h = (const double*)(p->d_tables + bi.k0h);
       for (int k = 0; k < 3; ++k) rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
     }
 

@@ -29,7 +29,7 @@ struct BoxInfo {
   BoxGeom g;
   int pad = 2;
   size_t tw_x = 0, tw_y = 0, tw_m = 0, tw_m64 = 0;  // offsets into the table block
-  size_t zt = 0, zt64[3] = {0, 0, 0};
+  size_t zt = 0, zt64[3] = {0, 0, 0}, k0h = 0;
   size_t ws_off = 0;   // half spectrum (plain: padded spectrum)
   size_t ws2_off = 0;  // plain: unpadded half spectrum
   size_t part_off = 0;
