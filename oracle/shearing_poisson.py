@@ -8,8 +8,9 @@ It computes, slowly and obviously, what the paper's method computes (Rendon Rest
 Gressel, "An efficient spectral Poisson solver for the NIRVANA code: the shearing-box case
 with vertical vacuum boundary conditions"):
 
-  1. map the density to the fully periodic (shearing) frame, Sect. 2.1: a spectral y-shift
-     by -Delta_y0(t) x / Lx, the Fourier-interpolation (SAFI) variant of the remap;
+  1. map the density to the fully periodic (shearing) frame, Sect. 2.1: a y-shift by
+     -Delta_y0(t) x / Lx, either spectral (the Fourier-interpolation, SAFI, variant) or by
+     linear interpolation between neighbouring y cells (the other variant the section names);
   2. Hockney zero padding of z from Nz to M = P*Nz cells, Sect. 2.2 and Sect. 2.4;
   3. forward transform in y (real half spectrum), x and z;
   4. multiply by the Green's function evaluated at the sheared wave vector
@@ -61,6 +62,7 @@ class Box:
     pad: int = 2            # P: z is padded from Nz to P*Nz cells
     alpha: float = 0.0      # L = alpha*Lz; 0 selects alpha = P/2
     method: str = "vgf"     # "vgf" (VGF-HybridBC) or "sasha"
+    remap: str = "spectral"  # map to the periodic frame: "spectral" (Fourier shift) or "linear"
 
     @property
     def m(self) -> int:
@@ -163,6 +165,19 @@ def sasha_phi0(rho: np.ndarray, box: Box, G: float) -> np.ndarray:
     return FOUR_PI * G * mean * z * (0.5 * z - z0)
 
 
+def shift_y_linear(f: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """Sample f[i, :, :] at the fractional y index j + d[i] by linear interpolation between the
+    two neighbouring cells (periodic in y): the real-space remap of Sect. 2.1 (linear variant)."""
+    ny = f.shape[1]
+    out = np.empty_like(f)
+    j = np.arange(ny)
+    for i in range(f.shape[0]):
+        m = math.floor(d[i])
+        w = d[i] - m
+        out[i] = (1.0 - w) * f[i, (j + m) % ny, :] + w * f[i, (j + m + 1) % ny, :]
+    return out
+
+
 def solve(rho: np.ndarray, box: Box, shear: Shear) -> np.ndarray:
     """Potential Phi on the Nx x Ny x Nz box for density rho (C order [x][y][z]), in FP64."""
     rho = np.asarray(rho, dtype=np.float64)
@@ -174,10 +189,18 @@ def solve(rho: np.ndarray, box: Box, shear: Shear) -> np.ndarray:
     x, _, _ = cell_centres(box)
     k, kz, Ky = sheared_wavenumbers(box, s)
 
-    # 1. Map to the periodic frame: y spectrum, shift by -s x (Sect. 2.1), drop the y-Nyquist.
-    rt = np.fft.rfft(rho, axis=1)[:, : ny // 2, :]
-    remap = np.exp(-1j * s * np.outer(x, Ky))
-    rt = rt * remap[:, :, None]
+    # 1. Map to the periodic frame (Sect. 2.1): the periodic field at (x, y) is the lab field at
+    #    (x, y - s x).  Spectral: multiply the y spectrum by exp(-i Ky s x).  Linear: sample the
+    #    lab field at y - s x by linear interpolation in y.  Then drop the y-Nyquist.
+    if box.remap == "spectral":
+        rt = np.fft.rfft(rho, axis=1)[:, : ny // 2, :]
+        remap = np.exp(-1j * s * np.outer(x, Ky))
+        rt = rt * remap[:, :, None]
+    elif box.remap == "linear":
+        cells = s * x / (box.ly / ny)  # shift s x in y cells
+        rt = np.fft.rfft(shift_y_linear(rho, -cells), axis=1)[:, : ny // 2, :]
+    else:
+        raise ValueError(box.remap)
 
     # 2. Zero padding of z to M = P*Nz (Hockney).
     rp = np.zeros((nx, ny // 2, M), dtype=np.complex128)
@@ -198,11 +221,15 @@ def solve(rho: np.ndarray, box: Box, shear: Shear) -> np.ndarray:
     # 5. Inverse transforms (z, x) and extraction of the physical cells.
     ph = np.fft.ifft(np.fft.ifft(ph, axis=2), axis=0)[:, :, :nz]
 
-    # 6. Reverse mapping and inverse y transform; scale by 4 pi G.
-    ph = ph * np.conj(remap)[:, :, None]
+    # 6. Reverse mapping and inverse y transform; scale by 4 pi G.  The lab potential at (x, y)
+    #    is the periodic one at (x, y + s x).
+    if box.remap == "spectral":
+        ph = ph * np.conj(remap)[:, :, None]
     full = np.zeros((nx, ny // 2 + 1, nz), dtype=np.complex128)
     full[:, : ny // 2, :] = ph
     phi = np.fft.irfft(full, n=ny, axis=1) * (FOUR_PI * shear.G)
+    if box.remap == "linear":
+        phi = shift_y_linear(phi, cells)
 
     if box.method == "sasha":
         phi = phi + sasha_phi0(rho, box, shear.G)[None, None, :]

@@ -11,6 +11,7 @@ import oracle.shearing_poisson as sp
 from . import test_oracle_bruteforce as tb
 from . import test_oracle_green as tg
 from . import test_oracle_physics as tp
+from . import test_oracle_remap_linear as tl
 
 
 ORIG_GREEN = sp.green_vgf
@@ -18,6 +19,7 @@ ORIG_MODES = sp.mode_numbers
 ORIG_OFFSET = sp.shear_offset
 ORIG_WAVENUMBERS = sp.sheared_wavenumbers
 ORIG_PHI0 = sp.sasha_phi0
+ORIG_SHIFT = sp.shift_y_linear
 
 
 def green_wrong_sign_sin(k, kz, L):
@@ -52,6 +54,16 @@ def phi0_box_mean(rho, box, G):
     return ORIG_PHI0(rho, box, G) * box.pad
 
 
+def shift_wrong_direction(f, d):
+    # interpolates at j - d instead of j + d
+    return ORIG_SHIFT(f, -np.asarray(d))
+
+
+def shift_nearest_cell(f, d):
+    # rounds to the nearest cell instead of interpolating
+    return ORIG_SHIFT(f, np.round(np.asarray(d)))
+
+
 def _fails(fn, *args):
     try:
         fn(*args)
@@ -73,6 +85,9 @@ def _fails(fn, *args):
         ("shear_offset", offset_negated, lambda: tp.test_shear_offset_wraps_into_box()),
         ("sasha_phi0", phi0_box_mean, lambda: tp.test_sasha_phi0_solves_its_equation()),
         ("sasha_phi0", phi0_box_mean, lambda: tb.test_oracle_equals_brute_force(tb.CASES[3])),
+        ("shift_y_linear", shift_wrong_direction,
+         lambda: tl.test_linear_equals_spectral_for_whole_cell_shifts((8, 32, 4, 1.0, 4.0, 1.0, 2.0, 1.0, 1.0), "vgf")),
+        ("shift_y_linear", shift_nearest_cell, lambda: tl.test_linear_remap_converges_at_second_order()),
     ],
 )
 def test_pin_catches_mutation(monkeypatch, attr, mutant, pin):
@@ -83,7 +98,7 @@ def test_pin_catches_mutation(monkeypatch, attr, mutant, pin):
 
     if hasattr(oracle, attr):
         monkeypatch.setattr(oracle, attr, mutant)
-    for mod in (tb, tg, tp):
+    for mod in (tb, tg, tp, tl):
         if hasattr(mod, attr):
             monkeypatch.setattr(mod, attr, mutant)
     assert _fails(pin), f"pin did not catch mutated {attr}"
