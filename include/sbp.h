@@ -25,7 +25,9 @@
  *   - cell centres x_i = (i+1/2) Lx/Nx, y_j = (j+1/2) Ly/Ny, z_k = -Lz/2 + (k+1/2) Lz/Nz;
  *   - the y-Nyquist row is dropped; x and z mode numbers run 0..n/2-1, -n/2..-1;
  *   - discrete normalisation Phi = 4 pi G IDFT(G DFT(rho_padded));
- *   - SASHA's mean is over the padded domain, <rho> = sum(rho)/(Nx Ny M).
+ *   - SASHA's mean is over the padded domain, <rho> = sum(rho)/(Nx Ny M);
+ *   - linear remap: row x_i is shifted by s x_i / dy y cells, interpolated between floor and
+ *     floor + 1 of the sampled position.
  *
  * Memory: rho and phi are caller-owned DEVICE buffers in C order [nx][ny][nz] (z fastest),
  * element type float for SBP_FP32 plans and double for SBP_FP64 plans.  rho is only read;
@@ -57,6 +59,12 @@ typedef enum {
 
 typedef enum { SBP_FP64 = 0, SBP_FP32 = 1 } sbp_precision;
 typedef enum { SBP_VGF = 0, SBP_SASHA = 1 } sbp_method;
+/* Mapping to the periodic frame (Sect. 2.1 names both): the periodic field at (x, y) is the lab
+ * field at (x, y - s x).  SPECTRAL multiplies the y spectrum by exp(-i Ky s x) (Fourier
+ * interpolation); LINEAR samples the lab field at y - s x by linear interpolation between the
+ * two neighbouring y cells (periodic in y) before the y transform, and the potential back at
+ * y + s x after it.  Both use the sheared wave vector kx = Kx + s Ky in the Green's function. */
+typedef enum { SBP_REMAP_SPECTRAL = 0, SBP_REMAP_LINEAR = 1 } sbp_remap;
 
 /* Plan flags. */
 #define SBP_FLAG_GRAPH 0x1u    /* capture the solve once into a HIP graph; replay per call      */
@@ -73,7 +81,7 @@ typedef enum { SBP_VGF = 0, SBP_SASHA = 1 } sbp_method;
                                    for SBP_FP32, five-pass for SBP_FP64 (the faster on gfx950).
                                    Both flags together are SBP_E_ARG. */
 
-/* Geometry and method of one box.
+/* Geometry, method and remap of one box.
  *   nx, ny: horizontal cells, each in {8,12,16,24,32,48,64,96,128,192,256,384,512,768,1024};
  *   nz:     vertical cells, even, >= 4, with pad*nz in the same set;
  *   lx, ly, lz: box lengths, > 0 and finite;
@@ -81,13 +89,15 @@ typedef enum { SBP_VGF = 0, SBP_SASHA = 1 } sbp_method;
  *   alpha:  truncation L = alpha*lz of the VGF kernel (Sect. 2.3); 0 selects pad/2 (the padded
  *           half-period, so periodic images of the truncated kernel never reach the box);
  *           must satisfy 1 <= alpha <= pad/2 otherwise;
- *   method: sbp_method. */
+ *   method: sbp_method;
+ *   remap:  sbp_remap (the plain path supports SBP_REMAP_SPECTRAL only). */
 typedef struct {
   int32_t nx, ny, nz;
   double lx, ly, lz;
   int32_t pad;
   double alpha;
   int32_t method;
+  int32_t remap;
 } sbp_box;
 
 /* Per-solve parameters of one box: shear rate q, rotation Omega, time t, constant G.

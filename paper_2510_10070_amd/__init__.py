@@ -49,10 +49,12 @@ class Box:
     pad: int = 2
     alpha: float = 0.0
     method: str = "vgf"  # "vgf" or "sasha"
+    remap: str = "spectral"  # map to the periodic frame: "spectral" or "linear" (interpolation)
 
     def to_c(self) -> SbpBox:
         m = {"vgf": _lib.SBP_VGF, "sasha": _lib.SBP_SASHA}.get(self.method, -1)
-        return SbpBox(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.pad, self.alpha, m)
+        r = {"spectral": _lib.SBP_REMAP_SPECTRAL, "linear": _lib.SBP_REMAP_LINEAR}.get(self.remap, -1)
+        return SbpBox(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.pad, self.alpha, m, r)
 
 
 @dataclass(frozen=True)

@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "SBP_OK", 1: "SBP_E_ARG", 2: "SBP_E_SIZE", 3: "SBP_E_NOMEM", 
                 5: "SBP_E_HIP", 6: "SBP_E_STATE"}
 SBP_FP64, SBP_FP32 = 0, 1
 SBP_VGF, SBP_SASHA = 0, 1
+SBP_REMAP_SPECTRAL, SBP_REMAP_LINEAR = 0, 1
 SBP_FLAG_GRAPH, SBP_FLAG_AUTOTUNE, SBP_FLAG_PLAIN, SBP_FLAG_FIVE_PASS, SBP_FLAG_FUSED = 0x1, 0x2, 0x4, 0x8, 0x10
 
 # every symbol include/sbp.h declares
@@ -23,7 +24,8 @@ EXPORTS = ("sbp_plan_create", "sbp_workspace_size", "sbp_set_workspace", "sbp_so
 class SbpBox(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
-                ("pad", ctypes.c_int32), ("alpha", ctypes.c_double), ("method", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("alpha", ctypes.c_double), ("method", ctypes.c_int32),
+                ("remap", ctypes.c_int32)]
 
 
 class SbpShear(ctypes.Structure):

@@ -39,10 +39,10 @@ int fused_ac_tiles(int prec, const BoxGeom& g, int variant) {
 }
 int fused_b_tiles(const BoxGeom& g) { return (g.nx / kFusedB16) * (g.ny / 2); }
 int fused_a(const BoxGeom& g) { return g.nx / kFusedB16; }
-hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st) {
-  return prec ? launch_fused_impl<float>(kind, len, a, variant, q, ga, blocks, recs, tw, tw2, st)
-              : launch_fused_impl<double>(kind, len, a, variant, q, ga, blocks, recs, tw, tw2, st);
+  return prec ? launch_fused_impl<float>(kind, len, a, variant, q, lin, ga, blocks, recs, tw, tw2, st)
+              : launch_fused_impl<double>(kind, len, a, variant, q, lin, ga, blocks, recs, tw, tw2, st);
 }
 
 }  // namespace sbp

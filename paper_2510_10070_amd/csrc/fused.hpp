@@ -54,7 +54,7 @@ struct PlanePhase {
 // keeps the remapped half spectra of its positions for all A planes in registers.  Finally the
 // A-point DFT across planes, the w_Nx^(j k1) twiddle and the store to W[k1][my][j][z].
 
-template <typename T, int NY, int A, int B, int V>
+template <typename T, int NY, int A, int B, int V, bool LIN>
 __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
   constexpr int ZC = fa_zc<T, V>();
@@ -102,12 +102,17 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
     // PG thread groups transform planes a0 .. a0+PG-1 (x = j + B a) into their LDS tiles
     const int x = j + B * (a0 + sub);
     const T* src = rho + (size_t)x * NY * nz + z0;
+    // linear remap: the periodic field at y_j is the lab field at y_j - shy (x + 1/2) cells
+    constexpr bool lin = LIN;  // linear remap (one instantiation each: the spectral path keeps its registers)
+    YInterp yi;
+    if (lin) yi.init(-br->shy * (x + 0.5), NY);
     fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true>(
         mytile, tw, stid,
         [&](int e, int c) {
           cplx<T> v = mk<T>(T(0), T(0));
           if (2 * c < zn) {
-            v = *reinterpret_cast<const cplx<T>*>(src + (size_t)e * nz + 2 * c);
+            auto ld = [&](int y) { return *reinterpret_cast<const cplx<T>*>(src + (size_t)y * nz + 2 * c); };
+            v = lin ? yi.sample<T>(e, NY, ld) : ld(e);
             if (sasha) {
               const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
               s0 += (double)v.x + (double)v.y;
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
 // A-point inverse DFT across k1 in registers, then per plane: reverse remap, Hermitian columns
 // in LDS, inverse y transform straight to phi (+ Phi_0 for SASHA).
 
-template <typename T, int NY, int A, int B, int V>
+template <typename T, int NY, int A, int B, int V, bool LIN>
 __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
   constexpr int ZC = fa_zc<T, V>();
@@ -301,19 +306,34 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
     // PG thread groups run the inverse y transforms of their planes straight to phi
     const int x = j + B * (a0 + sub);
     T* dst = phi + (size_t)x * NY * nz + z0;
-    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
-        mytile, tw, stid, [&](int e, int c) { return mytile[L::at(e, c)]; },
-        [&](int e, int c, cplx<T> v) {
-          if (2 * c < zn) {
-            if (sasha) {
-              const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
-              const double zb = za + dz;
-              v.x = (T)((double)v.x + (c2 * za + c1) * za);
-              v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
-            }
-            *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
-          }
-        });
+    auto store = [&](int e, int c, cplx<T> v) {
+      if (2 * c < zn) {
+        if (sasha) {
+          const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
+          const double zb = za + dz;
+          v.x = (T)((double)v.x + (c2 * za + c1) * za);
+          v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
+        }
+        *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
+      }
+    };
+    if constexpr (LIN) {
+      // linear remap: the lab potential at y_j is the periodic one at y_j + shy (x + 1/2)
+      // cells, so the transformed columns stay in LDS for the interpolation
+      YInterp yi;
+      yi.init(br->shy * (x + 0.5), NY);
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true>(
+          mytile, tw, stid, [&](int e, int c) { return mytile[L::at(e, c)]; },
+          [&](int e, int c, cplx<T> v) { mytile[L::at(e, c)] = v; });
+      __syncthreads();
+      for (int w = stid; w < NY * NB; w += TNT) {
+        const int c = w % NB, e = w / NB;
+        store(e, c, yi.sample<T>(e, NY, [&](int y) { return mytile[L::at(y, c)]; }));
+      }
+    } else {
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
+          mytile, tw, stid, [&](int e, int c) { return mytile[L::at(e, c)]; }, store);
+    }
     __syncthreads();  // the tiles are rebuilt for the next planes
   }
 }
@@ -530,11 +550,11 @@ __global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restri
 }
 
 template <typename T>
-hipError_t launch_fused_impl(int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+hipError_t launch_fused_impl(int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                              const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
-template <> hipError_t launch_fused_impl<float>(int, int, int, int, int, GroupArgs, int, const BoxRec*, const void*,
+template <> hipError_t launch_fused_impl<float>(int, int, int, int, int, bool, GroupArgs, int, const BoxRec*, const void*,
                                                 const void*, hipStream_t);
-template <> hipError_t launch_fused_impl<double>(int, int, int, int, int, GroupArgs, int, const BoxRec*, const void*,
+template <> hipError_t launch_fused_impl<double>(int, int, int, int, int, bool, GroupArgs, int, const BoxRec*, const void*,
                                                  const void*, hipStream_t);
 
 template <typename T> int fused_ac_tiles_t(const BoxGeom& g, int variant) {

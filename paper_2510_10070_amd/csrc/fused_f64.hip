@@ -7,7 +7,7 @@ namespace sbp {
 // a = A = Nx/16.  tw: y twiddles (A, C) or z twiddles (B); tw2: x twiddles (A, C) or the
 // double z twiddles (B).
 template <>
-hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                                  const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st) {
   using T = double;
   constexpr int B = kFusedB16;
@@ -27,11 +27,16 @@ hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int 
     return hipErrorInvalidValue;
   }
   const cplx<T>* t2 = static_cast<const cplx<T>*>(tw2);
-#define SBP_AC(NY_, A_)                                                                                     \
-  if (len == NY_ && a == A_) {                                                                               \
-    if (kind == 0) hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2); \
-    else hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);          \
-    return hipGetLastError();                                                                               \
+#define SBP_AC(NY_, A_)                                                                                          \
+  if (len == NY_ && a == A_) {                                                                                    \
+    if (kind == 0) {                                                                                              \
+      if (lin) hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, true>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2); \
+      else hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, false>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);   \
+    } else {                                                                                                      \
+      if (lin) hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0, true>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2); \
+      else hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0, false>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);   \
+    }                                                                                                             \
+    return hipGetLastError();                                                                                     \
   }
 #define SBP_NY(NY_) SBP_AC(NY_, 1) SBP_AC(NY_, 2) SBP_AC(NY_, 4) SBP_AC(NY_, 8) SBP_AC(NY_, 16)
   SBP_NY(16) SBP_NY(32) SBP_NY(64) SBP_NY(128) SBP_NY(256) SBP_NY(512)

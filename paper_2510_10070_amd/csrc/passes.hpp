@@ -90,6 +90,31 @@ __device__ __forceinline__ void remap_phase(int my, int x, double fy, double& cs
   sn = -sv;
 }
 
+// Linear remap (Sect. 2.1, interpolation variant): row values sampled at the fractional y index
+// j + d, periodic in n, as (1 - w) f[(j + m) mod n] + w f[(j + m + 1) mod n], m = floor(d).
+struct YInterp {
+  int m = 0;
+  double w = 0.0;
+  __device__ __forceinline__ void init(double d, int n) {
+    const double fl = floor(d);
+    w = d - fl;
+    long long mm = static_cast<long long>(fl) % n;
+    if (mm < 0) mm += n;
+    m = static_cast<int>(mm);
+  }
+  __device__ __forceinline__ int at(int j, int n) const {
+    const int a = j + m;
+    return a >= n ? a - n : a;
+  }
+  template <typename T, class F> __device__ __forceinline__ cplx<T> sample(int j, int n, F&& f) const {
+    const int j0 = at(j, n);
+    const int j1 = j0 + 1 == n ? 0 : j0 + 1;
+    const cplx<T> a = f(j0), b = f(j1);
+    const T wb = static_cast<T>(w), wa = T(1) - wb;
+    return mk<T>(wa * a.x + wb * b.x, wa * a.y + wb * b.y);
+  }
+};
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
@@ -168,10 +193,16 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
 
   const T* src = rho + (size_t)x * NY * nz + z0;
   const int zn = min(ZC, nz - z0);
+  // linear remap: the periodic field at y_j is the lab field at y_j - shy (x + 1/2) cells
+  const bool lin = REMAP && g.remap == 1;
+  YInterp yi;
+  if (lin) yi.init(-br->shy * (x + 0.5), NY);
   fft_run<T, NY, typename Fwd<NY>::L, L, NT, -1, false, true>(
       tile, tw, tid,
       [&](int e, int c) {
-        return 2 * c < zn ? *reinterpret_cast<const cplx<T>*>(src + (size_t)e * nz + 2 * c) : mk<T>(T(0), T(0));
+        if (2 * c >= zn) return mk<T>(T(0), T(0));
+        auto ld = [&](int y) { return *reinterpret_cast<const cplx<T>*>(src + (size_t)y * nz + 2 * c); };
+        return lin ? yi.sample<T>(e, NY, ld) : ld(e);
       },
       [&](int e, int c, cplx<T> v) { tile[L::at(e, c)] = v; });
   __syncthreads();
@@ -272,19 +303,34 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   }
   const double dz = g.lz / nz;
   T* dst = phi + (size_t)x * NY * nz + z0;
-  fft_run<T, NY, typename Fwd<NY>::L, L, NT, +1, true, false>(
-      tile, tw, tid, [&](int e, int c) { return tile[L::at(e, c)]; },
-      [&](int e, int c, cplx<T> v) {
-        if (2 * c < zn) {
-          if (sasha) {
-            const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
-            const double zb = za + dz;
-            v.x = (T)((double)v.x + (c2 * za + c1) * za);
-            v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
-          }
-          *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
-        }
-      });
+  auto store = [&](int e, int c, cplx<T> v) {
+    if (2 * c < zn) {
+      if (sasha) {
+        const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
+        const double zb = za + dz;
+        v.x = (T)((double)v.x + (c2 * za + c1) * za);
+        v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
+      }
+      *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
+    }
+  };
+  if (REMAP && g.remap == 1) {
+    // linear remap: the lab potential at y_j is the periodic one at y_j + shy (x + 1/2) cells,
+    // so the transformed columns stay in LDS for the interpolation
+    YInterp yi;
+    yi.init(br->shy * (x + 0.5), NY);
+    fft_run<T, NY, typename Fwd<NY>::L, L, NT, +1, true, true>(
+        tile, tw, tid, [&](int e, int c) { return tile[L::at(e, c)]; },
+        [&](int e, int c, cplx<T> v) { tile[L::at(e, c)] = v; });
+    __syncthreads();
+    for (int w = tid; w < NY * NB; w += NT) {
+      const int c = w % NB, e = w / NB;
+      store(e, c, yi.sample<T>(e, NY, [&](int y) { return tile[L::at(y, c)]; }));
+    }
+  } else {
+    fft_run<T, NY, typename Fwd<NY>::L, L, NT, +1, true, false>(
+        tile, tw, tid, [&](int e, int c) { return tile[L::at(e, c)]; }, store);
+  }
 }
 
 // ------------------------------------------------------------------------------------------

@@ -13,6 +13,7 @@ struct BoxGeom {
   int nx, ny, nz;  // physical cells; ny/2 stored y modes (Nyquist dropped)
   int m;           // padded z length P*nz
   int method;      // 0 = VGF-HybridBC, 1 = SASHA
+  int remap;       // 0 = spectral phase, 1 = linear interpolation in y
   double lx, ly, lz;
   double L;        // truncation length alpha*lz of the VGF kernel
 };
@@ -30,7 +31,8 @@ struct BoxRec {
   const void* rho;
   void* phi;
   double s;        // Delta_y0/Lx: kx = Kx + s Ky
-  double fy;       // Delta_y0/(2 Ly Nx): remap phase in cycles per unit of my*(2i+1)
+  double fy;       // Delta_y0/(2 Ly Nx): remap phase in cycles per unit of my*(2i+1) (0: linear remap)
+  double shy;      // linear remap: row x_i is shifted by shy (i + 1/2) y cells (s dx/dy)
   double scale;    // 4 pi G/(Nx Ny M)
   double fourpiG;
   // plan constants
@@ -81,7 +83,7 @@ bool fused_ok(const BoxGeom& g);
 int fused_ac_tiles(int prec, const BoxGeom& g, int variant);
 int fused_b_tiles(const BoxGeom& g);
 int fused_a(const BoxGeom& g);
-hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, GroupArgs ga, int blocks,
+hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
 
 // Copy the records of one solve from pinned ring slot `slot` (or, with slot < 0, from the slot

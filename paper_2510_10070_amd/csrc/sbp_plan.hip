@@ -122,6 +122,8 @@ sbp_status validate_box(const sbp_box& b, int i, int prec) {
                 "box %d: alpha=%g outside [1, pad/2]: periodic images of the truncated kernel would reach the box",
                 i, b.alpha);
   if (b.method != SBP_VGF && b.method != SBP_SASHA) return fail(SBP_E_ARG, "box %d: unknown method %d", i, b.method);
+  if (b.remap != SBP_REMAP_SPECTRAL && b.remap != SBP_REMAP_LINEAR)
+    return fail(SBP_E_ARG, "box %d: unknown remap %d", i, b.remap);
   const double n = (double)b.nx * b.ny * b.nz;
   if (n * elem_size(prec) > 64.0 * (1ull << 30)) return fail(SBP_E_SIZE, "box %d: grid too large", i);
   return SBP_OK;
@@ -267,19 +269,23 @@ void build_launches(sbp_plan p) {
   for (int phase = 0; phase < 5; ++phase)
   for (int kind = 0; kind < sbp::kKinds; ++kind) {
     if (sbp::kPhase[kind] != phase) continue;
-    // group key: transform length, tile variant, padding (z kinds), A (fused kinds)
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    // group key: transform length, tile variant, padding (z kinds), A (fused kinds), linear
+    // remap (fused passes A and C)
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
     for (int b = 0; b < nb; ++b) {
       const BoxInfo& bi = p->boxes[b];
       if (!kind_applies(bi, kind)) continue;
       const int q = (kind == sbp::kZ || kind == sbp::kFB) ? bi.pad : 0;
       const int a = kind >= sbp::kFA ? sbp::fused_a(bi.g) : 0;
-      groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a)].push_back(b);
+      const int lin = (kind == sbp::kFA || kind == sbp::kFC) && bi.g.remap == SBP_REMAP_LINEAR;
+      groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a, lin)].push_back(b);
     }
     for (auto& kv : groups) {
       Launch l;
       l.kind = kind;
-      std::tie(l.len, l.variant, l.q, l.a) = kv.first;
+      int lin = 0;
+      std::tie(l.len, l.variant, l.q, l.a, lin) = kv.first;
+      l.lin = lin != 0;
       l.n = (int)kv.second.size();
       l.ints_off = p->ints.size();
       for (int b : kv.second) p->ints.push_back(b);
@@ -320,7 +326,7 @@ hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
     case sbp::kZ:
       return sbp::launch_z(p->prec, l.len, l.variant, l.q, ga, l.blocks, p->d_recs, T + l.tw, T + l.tw64, st);
     default:
-      return sbp::launch_fused(p->prec, l.kind - sbp::kFA, l.len, l.a, l.variant, l.q, ga, l.blocks, p->d_recs,
+      return sbp::launch_fused(p->prec, l.kind - sbp::kFA, l.len, l.a, l.variant, l.q, l.lin, ga, l.blocks, p->d_recs,
                                T + l.tw, T + l.tw64, st);
   }
 }
@@ -386,7 +392,8 @@ sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, c
     hs[r].rho = rho[b];
     hs[r].phi = phi[b];
     hs[r].s = d / g.lx;
-    hs[r].fy = (d / g.ly) / (2.0 * g.nx);
+    hs[r].fy = g.remap == SBP_REMAP_LINEAR ? 0.0 : (d / g.ly) / (2.0 * g.nx);
+    hs[r].shy = (d / g.lx) * (g.lx / g.nx) / (g.ly / g.ny);
     hs[r].fourpiG = 4.0 * M_PI * s.G;
     hs[r].scale = hs[r].fourpiG / ((double)g.nx * g.ny * g.m);
   }
@@ -563,6 +570,8 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       return fail(SBP_E_ARG, "SBP_FLAG_FIVE_PASS and SBP_FLAG_FUSED are exclusive");
     if ((flags & SBP_FLAG_PLAIN) && (precision != SBP_FP64 || nbox != 1 || (flags & (SBP_FLAG_FIVE_PASS | SBP_FLAG_FUSED))))
       return fail(SBP_E_ARG, "the plain path is FP64, single-box and takes no schedule flag");
+    if ((flags & SBP_FLAG_PLAIN) && boxes[0].remap != SBP_REMAP_SPECTRAL)
+      return fail(SBP_E_ARG, "the plain path implements the spectral remap only");
     if (device < 0) return fail(SBP_E_ARG, "device=%d", device);
     const int prec = precision == SBP_FP32 ? 1 : 0;
     for (int i = 0; i < nbox; ++i) {
@@ -588,7 +597,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       const int pad = b.pad == 0 ? 2 : b.pad;
       const double alpha = b.alpha == 0.0 ? 0.5 * pad : b.alpha;
       bi.pad = pad;
-      bi.g = sbp::BoxGeom{b.nx, b.ny, b.nz, pad * b.nz, b.method, b.lx, b.ly, b.lz, alpha * b.lz};
+      bi.g = sbp::BoxGeom{b.nx, b.ny, b.nz, pad * b.nz, b.method, b.remap, b.lx, b.ly, b.lz, alpha * b.lz};
       bi.tw_x = tb.twiddle(b.nx, prec);
       bi.tw_y = tb.twiddle(b.ny, prec);
       bi.tw_m = tb.twiddle(pad * b.nz, prec);

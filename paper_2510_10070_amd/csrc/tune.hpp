@@ -19,6 +19,7 @@ constexpr int kPhase[kKinds] = {0, 1, 2, 3, 4, 0, 2, 4};
 // one kernel launch of the solve sequence: a group of boxes sharing a kernel shape
 struct Launch {
   int kind = 0, len = 0, variant = 0, q = 0, a = 0;
+  bool lin = false;  // fused passes A and C: linear remap instantiation
   int blocks = 0;
   size_t ints_off = 0;  // offset (in ints) of box_ids[n] then starts[n+1] in the group int block
   int n = 0;

@@ -99,6 +99,14 @@ def test_bad_plan_arguments():
     assert st == 1
     st, _ = _create([good()], flags=_lib.SBP_FLAG_FUSED | _lib.SBP_FLAG_FIVE_PASS)  # exclusive schedules
     assert st == 1
+    lin = good()
+    lin.remap = _lib.SBP_REMAP_LINEAR
+    st, _ = _create([lin], prec=0, flags=_lib.SBP_FLAG_PLAIN)  # the plain path is spectral only
+    assert st == 1
+    bad = good()
+    bad.remap = 2
+    st, _ = _create([bad])
+    assert st == 1
     st, _ = _create([good()], nbox=0)
     assert st == 1
     h = ctypes.c_void_p()

@@ -229,3 +229,27 @@ def test_fused_is_selected_and_mixed_schedules():
         got, used = gpu_solve(boxes, rhos, shears, prec, graph=True, schedule="fused")
         for b, g, u, s in zip(boxes, got, used, shears):
             assert rel_l2(g, oracle_solve(b, u, s)) <= TOL[prec]
+
+
+# linear-interpolation remap (the real-space variant of Sect. 2.1) in both schedules; the
+# shears give fractional and whole-cell row shifts
+LINEAR_CASES = [
+    ((32, 32, 16, 1.0, 1.0, 1.0, 2, 0.0), (1.5, 1.0, 0.37, 1.0)),
+    ((16, 64, 32, 1.0, 4.0, 1.0, 2, 0.0), (2.0, 1.0, 1.0, 0.7)),    # s = 2: whole-cell shifts
+    ((48, 24, 12, 2.0, 1.0, 0.8, 2, 0.0), (1.5, 1.0, 0.81, 1.0)),   # five-pass only (nx = 48)
+    ((64, 16, 16, 1.0, 2.0, 1.0, 4, 1.5), (1.5, 1.0, 1.3, 1.0)),
+]
+
+
+@pytest.mark.parametrize("schedule", ["fused", "five_pass"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["vgf", "sasha"])
+@pytest.mark.parametrize("case", LINEAR_CASES, ids=lambda c: "x".join(map(str, c[0][:3])) + f"_t{c[1][2]}")
+def test_linear_remap_parity(case, method, precision, schedule):
+    shape, shear = case
+    box = dict(_box(shape, method), remap="linear")
+    rho = lognormal_density(shape[:3], shape[5], 0.2 * shape[5], seed=sum(shape[:3]) + 7)
+    got, used = gpu_solve(box, rho, shear, precision, schedule=schedule)
+    err = rel_l2(got[0], oracle_solve(box, used[0], shear))
+    print(f"{shape} linear {method} {precision} {schedule}: rel-L2 {err:.3e}")
+    assert err <= TOL[precision], err
