@@ -5,11 +5,14 @@ from .shearing_poisson import (  # noqa: F401
     Shear,
     FOUR_PI,
     cell_centres,
+    fill_ghosts,
+    gravity,
     green_sasha,
     green_vgf,
     mode_numbers,
     sasha_phi0,
     shear_offset,
+    shift_y_linear,
     sheared_wavenumbers,
     solve,
 )

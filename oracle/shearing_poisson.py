@@ -234,3 +234,45 @@ def solve(rho: np.ndarray, box: Box, shear: Shear) -> np.ndarray:
     if box.method == "sasha":
         phi = phi + sasha_phi0(rho, box, shear.G)[None, None, :]
     return phi
+
+
+# ------------------------------------------------------------------------------------------
+# Output for the hydrodynamics: vertical ghost cells and the gravitational acceleration.
+
+
+def fill_ghosts(phi: np.ndarray, ng: int) -> np.ndarray:
+    """Potential with ng ghost layers below and above the box (Sect. 2.4): in the ghost cells
+    the vertical gradient equals that of the last active cell, i.e. Phi continues linearly
+    with the slope between the two outermost active cells.  Returns [nx][ny][nz + 2 ng]."""
+    nx, ny, nz = phi.shape
+    out = np.empty((nx, ny, nz + 2 * ng))
+    out[:, :, ng:ng + nz] = phi
+    lo = phi[:, :, 1] - phi[:, :, 0]
+    hi = phi[:, :, nz - 1] - phi[:, :, nz - 2]
+    for g in range(1, ng + 1):
+        out[:, :, ng - g] = phi[:, :, 0] - g * lo
+        out[:, :, ng + nz - 1 + g] = phi[:, :, nz - 1] + g * hi
+    return out
+
+
+def gravity(phi_g: np.ndarray, box: Box, shear: Shear, ng: int):
+    """Acceleration g = -grad Phi at the cell centres by second-order centred differences,
+    from the potential with ng >= 1 ghost layers in z (as filled by fill_ghosts).
+
+    y is periodic.  x is shear-periodic: the lab field satisfies f(x + Lx, y) = f(x, y + Dy0),
+    so the neighbour beyond the last x row is the first row sampled at y + Dy0 and the one
+    before the first row is the last row sampled at y - Dy0, both by linear interpolation in y
+    (the real-space shift used by the linear remap).  z uses the ghost layers."""
+    if ng < 1:
+        raise ValueError("the z difference needs at least one ghost layer")
+    nx, ny, nz = box.nx, box.ny, box.nz
+    phi = phi_g[:, :, ng:ng + nz]
+    dx, dy, dz = box.lx / nx, box.ly / ny, box.lz / nz
+    cells = shear_offset(shear.q, shear.omega, box.lx, box.ly, shear.t) / dy
+    first = shift_y_linear(phi[:1], np.array([cells]))       # row 0 at y + Dy0
+    last = shift_y_linear(phi[-1:], np.array([-cells]))      # row nx-1 at y - Dy0
+    ext = np.concatenate([last, phi, first], axis=0)
+    gx = -(ext[2:] - ext[:-2]) / (2.0 * dx)
+    gy = -(np.roll(phi, -1, axis=1) - np.roll(phi, 1, axis=1)) / (2.0 * dy)
+    gz = -(phi_g[:, :, ng + 1:ng + nz + 1] - phi_g[:, :, ng - 1:ng + nz - 1]) / (2.0 * dz)
+    return gx, gy, gz

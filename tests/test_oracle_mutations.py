@@ -11,6 +11,7 @@ import oracle.shearing_poisson as sp
 from . import test_oracle_bruteforce as tb
 from . import test_oracle_green as tg
 from . import test_oracle_physics as tp
+from . import test_oracle_gravity as tgr
 from . import test_oracle_remap_linear as tl
 
 
@@ -88,6 +89,7 @@ def _fails(fn, *args):
         ("shift_y_linear", shift_wrong_direction,
          lambda: tl.test_linear_equals_spectral_for_whole_cell_shifts((8, 32, 4, 1.0, 4.0, 1.0, 2.0, 1.0, 1.0), "vgf")),
         ("shift_y_linear", shift_nearest_cell, lambda: tl.test_linear_remap_converges_at_second_order()),
+        ("shift_y_linear", shift_wrong_direction, lambda: tgr.test_gravity_second_order(0.41)),
     ],
 )
 def test_pin_catches_mutation(monkeypatch, attr, mutant, pin):
@@ -98,7 +100,7 @@ def test_pin_catches_mutation(monkeypatch, attr, mutant, pin):
 
     if hasattr(oracle, attr):
         monkeypatch.setattr(oracle, attr, mutant)
-    for mod in (tb, tg, tp, tl):
+    for mod in (tb, tg, tp, tl, tgr):
         if hasattr(mod, attr):
             monkeypatch.setattr(mod, attr, mutant)
     assert _fails(pin), f"pin did not catch mutated {attr}"
