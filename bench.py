@@ -172,6 +172,32 @@ def main() -> int:
         del rho, phi
         torch.cuda.empty_cache()
 
+    # acceleration -grad Phi from the FP32 potential (a streaming stencil: Phi in, three fields out)
+    grav = None
+    if args.only in (None, "fp32"):
+        plan = Plan(Box(nx, ny, nz, lx, ly, lz), precision="fp32")
+        rho = torch.tensor(rho64, dtype=torch.float32, device="cuda:0")
+        phi = torch.empty_like(rho)
+        g = [torch.empty_like(rho) for _ in range(3)]
+        plan.solve(rho, phi, shear)
+        for _ in range(5):
+            plan.gravity(phi, *g, shear)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(50):
+            plan.gravity(phi, *g, shear)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 50
+        gb = 4 * N * 4  # Phi read once, gx, gy, gz written
+        grav = {"us": round(ms * 1e3, 2), "gbs_alg": round(gb / (ms * 1e-3) / 1e9, 1), "bytes_alg": gb}
+        log(f"gravity fp32: {ms * 1e3:.1f} us, {grav['gbs_alg']:.0f} GB/s (algorithmic)")
+        plan.close()
+        del rho, phi, g
+        torch.cuda.empty_cache()
+
     if args.only:
         r = res[args.only]
         print(json.dumps({"leg": args.only, "ms_per_step": round(r["ms"], 5), "solves_per_s": round(r["solves_per_s"], 1),
@@ -247,6 +273,7 @@ def main() -> int:
                                   "fp64": round(res["fp64"]["solves_per_s"] / res["plain_fp64"]["solves_per_s"], 2)},
         "fp32_linear_remap": {"solves_per_s": round(res["fp32_linear"]["solves_per_s"], 1),
                               "ms_per_step": round(res["fp32_linear"]["ms"], 5)},
+        "gravity_fp32": grav,
         "fp32_direct": {"solves_per_s": round(res["fp32_direct"]["solves_per_s"], 1),
                         "ms_per_step": round(res["fp32_direct"]["ms"], 5)},
         "fp64_direct": {"solves_per_s": round(res["fp64_direct"]["solves_per_s"], 1),

@@ -134,6 +134,25 @@ sbp_status sbp_set_workspace(sbp_plan plan, void* device_ptr, size_t bytes);
 sbp_status sbp_solve(sbp_plan plan, const void* const* rho, void* const* phi,
                      const sbp_shear* params, void* stream);
 
+/* Potential with ng ghost layers below and above the box (Sect. 2.4): in the ghost cells the
+ * vertical gradient equals that of the last active cell, i.e. Phi continues linearly with the
+ * slope between the two outermost active cells.
+ * phi[b]: device, [nx][ny][nz] (as written by sbp_solve); out[b]: device, [nx][ny][nz + 2 ng],
+ * the active cells at z offset ng; element type of the plan's precision; out must not overlap
+ * phi.  1 <= ng <= 16, else SBP_E_ARG.  Enqueued on `stream`. */
+sbp_status sbp_ghosts(sbp_plan plan, const void* const* phi, void* const* out, int32_t ng, void* stream);
+
+/* Gravitational acceleration g = -grad Phi of every box at the cell centres, by second-order
+ * centred differences: periodic in y; in z the values beyond the edges follow the ghost rule
+ * above (so the edge cells take the one-sided difference); shear-periodic in x, where the
+ * neighbour beyond the last x row is the first row sampled at y + Delta_y0 and the one before
+ * the first row is the last row sampled at y - Delta_y0, by linear interpolation in y.
+ * phi[b]: device, [nx][ny][nz]; gx[b], gy[b], gz[b]: device outputs of the same layout and
+ * type, not overlapping each other or phi; params[b]: the shear parameters of the solve (only
+ * Delta_y0 = fmod(q Omega Lx t, Ly) is used).  Enqueued on `stream`. */
+sbp_status sbp_gravity(sbp_plan plan, const void* const* phi, void* const* gx, void* const* gy, void* const* gz,
+                       const sbp_shear* params, void* stream);
+
 /* Free the plan and everything it allocated.  Call only after the stream used by its
  * solves has been synchronised.  NULL is accepted and ignored. */
 sbp_status sbp_plan_destroy(sbp_plan plan);

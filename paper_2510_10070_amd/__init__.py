@@ -134,6 +134,52 @@ class Plan:
         st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         _check(self._lib.sbp_solve(self._h, rp, pp, sp, ctypes.c_void_p(st)), "sbp_solve")
 
+    # -- output for the hydrodynamics ------------------------------------------------------
+    def _check_tensors(self, groups, shapes):
+        import torch
+
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        for name, ts in groups:
+            for b, t in enumerate(ts):
+                if not t.is_cuda or t.dtype != dt or tuple(t.shape) != shapes[b] or not t.is_contiguous():
+                    raise ValueError(f"box {b}: {name} must be a contiguous {dt} CUDA tensor of shape {shapes[b]}")
+
+    @staticmethod
+    def _stream(stream, t):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(t.device)
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+    def ghosts(self, phi, out, ng: int, stream=None) -> None:
+        """Potential with ng vertical ghost layers (sbp_ghosts): out has shape (nx, ny, nz + 2 ng)."""
+        phis = [phi] if not isinstance(phi, (list, tuple)) else list(phi)
+        outs = [out] if not isinstance(out, (list, tuple)) else list(out)
+        nb = len(self.boxes)
+        if not (len(phis) == len(outs) == nb):
+            raise ValueError(f"expected {nb} phi/out entries")
+        self._check_tensors([("phi", phis)], [(b.nx, b.ny, b.nz) for b in self.boxes])
+        self._check_tensors([("out", outs)], [(b.nx, b.ny, b.nz + 2 * ng) for b in self.boxes])
+        pp = (ctypes.c_void_p * nb)(*[p.data_ptr() for p in phis])
+        op = (ctypes.c_void_p * nb)(*[o.data_ptr() for o in outs])
+        _check(self._lib.sbp_ghosts(self._h, pp, op, ng, ctypes.c_void_p(self._stream(stream, phis[0]))),
+               "sbp_ghosts")
+
+    def gravity(self, phi, gx, gy, gz, shear: Union[Shear, Sequence[Shear]], stream=None) -> None:
+        """Acceleration -grad Phi (sbp_gravity) into gx, gy, gz, each shaped like phi."""
+        lists = [[v] if not isinstance(v, (list, tuple)) else list(v) for v in (phi, gx, gy, gz)]
+        shears = [shear] if isinstance(shear, Shear) else list(shear)
+        nb = len(self.boxes)
+        if any(len(v) != nb for v in lists) or len(shears) != nb:
+            raise ValueError(f"expected {nb} entries per argument")
+        shapes = [(b.nx, b.ny, b.nz) for b in self.boxes]
+        self._check_tensors(list(zip(("phi", "gx", "gy", "gz"), lists)), shapes)
+        arrs = [(ctypes.c_void_p * nb)(*[t.data_ptr() for t in v]) for v in lists]
+        sp = (SbpShear * nb)(*[SbpShear(s.q, s.omega, s.t, s.G) for s in shears])
+        _check(self._lib.sbp_gravity(self._h, *arrs, sp, ctypes.c_void_p(self._stream(stream, lists[0][0]))),
+               "sbp_gravity")
+
     # -- instrumentation -------------------------------------------------------------------
     def profile_enable(self, on: bool = True) -> None:
         _check(self._lib.sbp_profile_enable(self._h, 1 if on else 0), "sbp_profile_enable")

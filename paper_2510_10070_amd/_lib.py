@@ -18,7 +18,8 @@ SBP_FLAG_GRAPH, SBP_FLAG_AUTOTUNE, SBP_FLAG_PLAIN, SBP_FLAG_FIVE_PASS, SBP_FLAG_
 
 # every symbol include/sbp.h declares
 EXPORTS = ("sbp_plan_create", "sbp_workspace_size", "sbp_set_workspace", "sbp_solve", "sbp_plan_destroy",
-           "sbp_status_str", "sbp_last_error", "sbp_profile_enable", "sbp_profile_read", "sbp_plan_describe")
+           "sbp_status_str", "sbp_last_error", "sbp_profile_enable", "sbp_profile_read", "sbp_plan_describe",
+           "sbp_ghosts", "sbp_gravity")
 
 
 class SbpBox(ctypes.Structure):
@@ -66,5 +67,10 @@ def load() -> ctypes.CDLL:
     lib.sbp_profile_read.restype = ctypes.c_int
     lib.sbp_plan_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
     lib.sbp_plan_describe.restype = ctypes.c_int
+    lib.sbp_ghosts.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), i32, P]
+    lib.sbp_ghosts.restype = ctypes.c_int
+    lib.sbp_gravity.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                ctypes.POINTER(SbpShear), P]
+    lib.sbp_gravity.restype = ctypes.c_int
     _lib = lib
     return lib

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbp.so")
 SOURCES = ["sbp_plan.hip", "tune.hip", "dispatch.hip", "plain.hip", "pass_y_f32.hip", "pass_y_f64.hip",
            "pass_x_f32.hip", "pass_x_f64.hip", "pass_z_f32.hip", "pass_z_f64.hip",
-           "fused_f32.hip", "fused_f64.hip"]
+           "fused_f32.hip", "fused_f64.hip", "gravity.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

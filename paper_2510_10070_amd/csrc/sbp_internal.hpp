@@ -90,6 +90,11 @@ hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, 
 // named by ctl[0], which the kernel then advances) into the device record array.
 hipError_t launch_fetch(const BoxRec* ring, BoxRec* recs, int nrec, int nslots, int slot, int* ctl, hipStream_t st);
 
+// Output for the hydrodynamics: vertical ghost layers and the acceleration (gravity.hip).
+hipError_t launch_ghosts(int prec, const BoxGeom& g, const void* phi, void* out, int ng, hipStream_t st);
+hipError_t launch_gravity(int prec, const BoxGeom& g, double dy0, const void* phi, void* gx, void* gy, void* gz,
+                          hipStream_t st);
+
 // Plain (unfused) FP64 path for one box: rec0 views the half spectrum, rec_pad the padded one.
 constexpr int kPlainPartials = 1024;
 hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* d_rec0, const BoxRec* d_rec_pad, GroupArgs one,

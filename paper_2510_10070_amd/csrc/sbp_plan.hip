@@ -856,6 +856,61 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
   }
 }
 
+sbp_status sbp_ghosts(sbp_plan p, const void* const* phi, void* const* out, int32_t ng, void* stream) {
+  try {
+    if (!p) return fail(SBP_E_ARG, "NULL plan");
+    if (!phi || !out) return fail(SBP_E_ARG, "NULL phi/out array");
+    if (ng < 1 || ng > 16) return fail(SBP_E_ARG, "ng=%d outside [1, 16]", ng);
+    const size_t w = elem_size(p->prec);
+    for (size_t b = 0; b < p->boxes.size(); ++b) {
+      const sbp::BoxGeom& g = p->boxes[b].g;
+      if (!phi[b] || !out[b]) return fail(SBP_E_ARG, "box %zu: NULL phi or out", b);
+      const size_t rows = (size_t)g.nx * g.ny;
+      if (overlap(phi[b], rows * g.nz * w, out[b], rows * (g.nz + 2 * ng) * w))
+        return fail(SBP_E_ARG, "box %zu: out overlaps phi", b);
+    }
+    HIP_TRY(hipSetDevice(p->device));
+    for (size_t b = 0; b < p->boxes.size(); ++b)
+      HIP_TRY(sbp::launch_ghosts(p->prec, p->boxes[b].g, phi[b], out[b], ng, (hipStream_t)stream));
+    return SBP_OK;
+  } catch (...) {
+    return fail(SBP_E_STATE, "internal error");
+  }
+}
+
+sbp_status sbp_gravity(sbp_plan p, const void* const* phi, void* const* gx, void* const* gy, void* const* gz,
+                       const sbp_shear* params, void* stream) {
+  try {
+    if (!p) return fail(SBP_E_ARG, "NULL plan");
+    if (!phi || !gx || !gy || !gz || !params) return fail(SBP_E_ARG, "NULL argument array");
+    const size_t w = elem_size(p->prec);
+    for (size_t b = 0; b < p->boxes.size(); ++b) {
+      const sbp::BoxGeom& g = p->boxes[b].g;
+      const size_t n = (size_t)g.nx * g.ny * g.nz * w;
+      const void* ptr[4] = {phi[b], gx[b], gy[b], gz[b]};
+      for (int i = 0; i < 4; ++i) {
+        if (!ptr[i]) return fail(SBP_E_ARG, "box %zu: NULL pointer", b);
+        for (int k = 0; k < i; ++k)
+          if (overlap(ptr[i], n, ptr[k], n)) return fail(SBP_E_ARG, "box %zu: overlapping phi/gx/gy/gz", b);
+      }
+      const sbp_shear& s = params[b];
+      if (!std::isfinite(s.q * s.omega * g.lx * s.t)) return fail(SBP_E_ARG, "box %zu: non-finite shear", b);
+    }
+    HIP_TRY(hipSetDevice(p->device));
+    for (size_t b = 0; b < p->boxes.size(); ++b) {
+      const sbp::BoxGeom& g = p->boxes[b].g;
+      const sbp_shear& s = params[b];
+      double d = std::fmod(s.q * s.omega * g.lx * s.t, g.ly);
+      if (d < 0.0) d += g.ly;
+      if (d >= g.ly) d = 0.0;
+      HIP_TRY(sbp::launch_gravity(p->prec, g, d, phi[b], gx[b], gy[b], gz[b], (hipStream_t)stream));
+    }
+    return SBP_OK;
+  } catch (...) {
+    return fail(SBP_E_STATE, "internal error");
+  }
+}
+
 sbp_status sbp_plan_destroy(sbp_plan p) {
   if (!p) return SBP_OK;
   hipSetDevice(p->device);
