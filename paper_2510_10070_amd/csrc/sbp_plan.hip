@@ -649,9 +649,13 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       } else {
         bi.ws_off = ws;
         ws = align_up(ws + n * w);  // nx * (ny/2) * nz complex
+        // one partial-sum pair per tile of the first pass, for every tile variant the plan or
+        // the autotuner may pick (each pass-A/y tile writes its own slot)
         int most = 0;
-        for (int v = 0; v < sbp::kVariants; ++v) most = std::max(most, sbp::y_tiles(prec, bi.g, v));
-        most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, 0));
+        for (int v = 0; v < sbp::kVariants; ++v) {
+          most = std::max(most, sbp::y_tiles(prec, bi.g, v));
+          most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, v));
+        }
         bi.npartials = most;
       }
       bi.part_off = npart;
