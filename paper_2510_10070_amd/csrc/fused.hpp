@@ -81,8 +81,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   const int j = t / nzc;
   const int z0 = (t - j * nzc) * ZC;
   const int zn = min(ZC, nz - z0);
-  const T* rho = static_cast<const T*>(br->rho);
-  cplx<T>* W = static_cast<cplx<T>*>(br->W);
+  gmem<const T>* rho = hbm(static_cast<const T*>(br->rho));
+  gmem<cplx<T>>* W = hbm(static_cast<cplx<T>*>(br->W));
   const bool sasha = g.method == 1;
   const double dz = g.lz / nz;
   cplx<T>* mytile = tile + sub * SLOTS;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   for (int a0 = 0; a0 < A; a0 += PG) {
     // PG thread groups transform planes a0 .. a0+PG-1 (x = j + B a) into their LDS tiles
     const int x = j + B * (a0 + sub);
-    const T* src = rho + (size_t)x * NY * nz + z0;
+    gmem<const T>* src = rho + (size_t)x * NY * nz + z0;
     // linear remap: the periodic field at y_j is the lab field at y_j - shy (x + 1/2) cells
     constexpr bool lin = LIN;  // linear remap (one instantiation each: the spectral path keeps its registers)
     YInterp yi;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
         [&](int e, int c) {
           cplx<T> v = mk<T>(T(0), T(0));
           if (2 * c < zn) {
-            auto ld = [&](int y) { return *reinterpret_cast<const cplx<T>*>(src + (size_t)y * nz + 2 * c); };
+            auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * c); };
             v = lin ? yi.sample<T>(e, NY, ld) : ld(e);
             if (sasha) {
               const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
@@ -161,8 +161,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
         sa += red[0][i];
         sb += red[1][i];
       }
-      br->partials[2 * t] = sa;
-      br->partials[2 * t + 1] = sb;
+      hbm(br->partials)[2 * t] = sa;
+      hbm(br->partials)[2 * t + 1] = sb;
     }
   }
 
@@ -186,9 +186,9 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
     for (int k1 = 0; k1 < A; ++k1) {
       const cplx<T> w = twx[(j * k1) % nx];
       const cplx<T> ra = cmul<T>(va[k1], w), rb = cmul<T>(vb[k1], w);
-      cplx<T>* dst = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
+      gmem<cplx<T>>* dst = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
       if constexpr (sizeof(T) == 4) {
-        *reinterpret_cast<float4*>(dst) = make_float4(ra.x, ra.y, rb.x, rb.y);
+        *reinterpret_cast<gmem<float4>*>(dst) = make_float4(ra.x, ra.y, rb.x, rb.y);
       } else {
         dst[0] = ra;
         dst[1] = rb;
@@ -228,8 +228,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   const int j = t / nzc;
   const int z0 = (t - j * nzc) * ZC;
   const int zn = min(ZC, nz - z0);
-  const cplx<T>* W = static_cast<const cplx<T>*>(br->W);
-  T* phi = static_cast<T*>(br->phi);
+  gmem<const cplx<T>>* W = hbm(static_cast<const cplx<T>*>(br->W));
+  gmem<T>* phi = hbm(static_cast<T*>(br->phi));
   const int nx = g.nx;
   cplx<T>* mytile = tile + sub * SLOTS;
   load_twiddles<T, NY, NT>(tw, twy, tid);
@@ -246,10 +246,10 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
     for (int k1 = 0; k1 < A; ++k1) {
       va[k1] = vb[k1] = mk<T>(T(0), T(0));
       if (q < QN && 2 * c < zn) {
-        const cplx<T>* src = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
+        gmem<const cplx<T>>* src = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
         cplx<T> a0, b0;
         if constexpr (sizeof(T) == 4) {
-          const float4 v4 = *reinterpret_cast<const float4*>(src);
+          const float4 v4 = *reinterpret_cast<gmem<const float4>*>(src);
           a0 = mk<T>(v4.x, v4.y);
           b0 = mk<T>(v4.z, v4.w);
         } else {
@@ -273,8 +273,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   const bool sasha = g.method == 1;
   double c2 = 0.0, c1 = 0.0;
   if (sasha) {
-    c2 = br->coef->c2;
-    c1 = br->coef->c1;
+    c2 = hbm(br->coef)->c2;
+    c1 = hbm(br->coef)->c1;
   }
   const double dz = g.lz / nz;
 #pragma unroll
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
     __syncthreads();
     // PG thread groups run the inverse y transforms of their planes straight to phi
     const int x = j + B * (a0 + sub);
-    T* dst = phi + (size_t)x * NY * nz + z0;
+    gmem<T>* dst = phi + (size_t)x * NY * nz + z0;
     auto store = [&](int e, int c, cplx<T> v) {
       if (2 * c < zn) {
         if (sasha) {
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
           v.x = (T)((double)v.x + (c2 * za + c1) * za);
           v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
         }
-        *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
+        *reinterpret_cast<gmem<cplx<T>>*>(dst + (size_t)e * nz + 2 * c) = v;
       }
     };
     if constexpr (LIN) {
@@ -339,14 +339,15 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
 }
 
 // ------------------------------------------------------------------------------------------
-// Pass B: one block per (k1, my).  The B-point DFT across the j pencils runs in registers
-// (one thread per z) and parks the B pencils in the LDS tile.  Every wavefront then takes
-// pairs of pencil groups (PW pencils each): it lifts the inputs of both groups into registers,
-// uses the tile area of the pair as its exchange buffer for the padded z transform, the Green
-// multiply for Kx = k1 + A k2 and the inverse of each group in turn, and writes both results
-// back; no workgroup barrier and no LDS beyond the tile.  A final barrier, and the inverse
-// B-point DFT goes back to HBM.  Float plans take the k = 0 pencil (tile 0, pencil 0) in
-// double as a direct convolution with the time-independent real-space kernel h.
+// Pass B: one block per (k1, my) item.
+// The B-point DFT across the j pencils runs in registers (one thread per z) and parks the B
+// pencils in the LDS tile.  Every wavefront then takes tuples of Q pencil groups (PW pencils
+// each): it lifts the inputs of the tuple into registers, uses the tuple's tile area as its
+// exchange buffer for the padded z transform, the Green multiply for Kx = k1 + A k2 and the
+// inverse of each group in turn, and writes the results back; no workgroup barrier and no LDS
+// beyond the tile.  A barrier, and the inverse B-point DFT goes back to HBM.  Float plans take
+// the k = 0 pencil (tile 0, pencil 0) in double as a direct convolution with the
+// time-independent real-space kernel h.
 
 // pencils per transform (about eight points per lane; Q such groups share one tile area, whose
 // Q * PW * Nz slots are exactly one group's padded exchange buffer) and wavefronts per block
@@ -358,75 +359,61 @@ template <int M, int B, int Q> constexpr int fb_tuples() { return B / (Q * fb_pw
 template <int M, int B, int Q> constexpr int fb_waves() { return fb_tuples<M, B, Q>() < 4 ? fb_tuples<M, B, Q>() : 4; }
 template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves<M, B, Q>(); }
 
+template <typename T, int M, int B, int Q> struct FbShared {
+  static constexpr int PW = fb_pw<M, B, Q>();
+  static constexpr int NZ = M / Q;
+  static constexpr bool kF32 = std::is_same<T, float>::value;
+  cplx<T> tile[lds_slots(B * NZ)];
+  cplx<T> tw[M];
+  T pa0[B], pe[B], pik[B], pk2[B], psp[B];  // Green's-function coefficients of the B modes
+};
+
+// one (k1, my) item of a box
+template <typename T> struct FbItem {
+  const BoxRec* br;
+  int t, k1, my;
+  gmem<cplx<T>>* base;  // the item's B pencils, B*Nz contiguous values
+  bool own0;      // float plans: this item holds Kx = Ky = 0 (pencil k2 = 0)
+};
+
 template <typename T, int M, int B, int Q>
-__global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                            const cplx<T>* __restrict__ twm, const double2* __restrict__ twm64,
-                                            int A) {
-  (void)twm64;
-  constexpr int PW = fb_pw<M, B, Q>();
-  constexpr int NTUP = fb_tuples<M, B, Q>();
-  constexpr int WV = fb_waves<M, B, Q>();
-  constexpr int NT = 64 * WV;
-  constexpr int NZ = M / Q;
-  constexpr int ZPT = (NZ + NT - 1) / NT;  // z columns per thread in the j transforms
-  constexpr bool kF32 = std::is_same<T, float>::value;
-  static_assert(Q * PW * NTUP == B, "groups must tile the B pencils");
-  using LT = Tile<B, 1, NZ, false>;  // parked pencils: element z of pencil k2
-  using LW = Tile<PW, 1, M, false>;  // one group's exchange layout inside its tuple's tile area
-  using RF = typename Fwd<M>::L;
-  using RI = typename Inv<M>::L;
-  using S0 = Stage<T, M, RF, 0, LW, 64, -1>;
-  using SL = Stage<T, M, RI, RI::n - 1, LW, 64, +1>;
-  constexpr int RIN = (S0::R % Q == 0) ? S0::R / Q : S0::R;
-  constexpr int ROUT = (SL::R % Q == 0) ? SL::R / Q : SL::R;
-  __shared__ cplx<T> tile[lds_slots(B * NZ)];
-  __shared__ cplx<T> tw[M];
-  __shared__ T pa0[B], pe[B], pik[B], pk2[B];
-  __shared__ int pzero[B];
-  __shared__ double d0[kF32 ? NZ : 1];  // float plans: real k = 0 pencil input in double
+__device__ __forceinline__ FbItem<T> fb_item(const BoxRec* br, int t) {
+  FbItem<T> it;
+  it.br = br;
+  it.t = t;
+  const int hy = br->g.ny / 2;
+  it.k1 = t / hy;
+  it.my = t - it.k1 * hy;
+  it.base = hbm(static_cast<cplx<T>*>(br->W)) + (size_t)t * B * (M / Q);
+  it.own0 = std::is_same<T, float>::value && t == 0;
+  return it;
+}
 
-  int t;
-  const BoxRec* br = group_box(ga, recs, t);
-  const BoxGeom g = br->g;
-  const int tid = threadIdx.x;
-  const int hy = g.ny / 2;
-  const int k1 = t / hy, my = t - k1 * hy;
+// Green's-function scalars of the B pencils (double, rounded once), and for SASHA the mean and
+// centre of mass from the pass-A partial sums (first wavefront of the box's first item)
+template <typename T, int M, int B, int Q>
+__device__ __forceinline__ void fb_scalars(FbShared<T, M, B, Q>& sh, const FbItem<T>& it, int A, int tid) {
+  const BoxRec* br = it.br;
+  const BoxGeom& g = br->g;
   const bool sasha = g.method == 1;
-  const double scale = br->scale;
-  cplx<T>* base = static_cast<cplx<T>*>(br->W) + (size_t)t * B * NZ;
-  const bool own0 = kF32 && t == 0;  // this block holds Kx = Ky = 0 (pencil k2 = 0)
-  load_twiddles<T, M, NT>(tw, twm, tid);
-
-  // Green's-function scalars of the B pencils (double, rounded once)
   if (tid < B) {
     const double two_pi = 6.283185307179586476925286766559;
-    const double Ky = (two_pi / g.ly) * my;
-    const int mx = k1 + A * tid;
+    const double Ky = (two_pi / g.ly) * it.my;
+    const int mx = it.k1 + A * tid;
     const int sx = mx < g.nx / 2 ? mx : mx - g.nx;
     const double kx = (two_pi / g.lx) * sx + br->s * Ky;
-    const double kk2 = kx * kx + Ky * Ky;
-    const double k = sqrt(kk2);
-    const int zero = (mx == 0 && my == 0);
-    pzero[tid] = zero;
-    pk2[tid] = (T)kk2;
-    if (!zero && !sasha) {
-      pa0[tid] = (T)(-expm1(-k * g.L) * scale);
-      pe[tid] = (T)(exp(-k * g.L) * scale);
-      pik[tid] = (T)(1.0 / k);
-    } else {
-      pa0[tid] = T(0);
-      pe[tid] = T(0);
-      pik[tid] = T(0);
-    }
+    const ModeGreen<T> c = mode_green<T>(kx * kx + Ky * Ky, mx == 0 && it.my == 0, sasha, g.L, br->scale);
+    sh.pa0[tid] = c.a0;
+    sh.pe[tid] = c.e;
+    sh.pik[tid] = c.ik;
+    sh.pk2[tid] = c.k2;
+    sh.psp[tid] = c.zero;
   }
-
-  // SASHA: <rho> and the centre of mass from the pass-A partial sums (first wavefront of the
-  // box's first block, fixed order)
-  if (sasha && t == 0 && tid < 64) {
+  if (sasha && it.t == 0 && tid < 64) {
     double a = 0.0, b = 0.0;
     for (int i = tid; i < br->npartials; i += 64) {
-      a += br->partials[2 * i];
-      b += br->partials[2 * i + 1];
+      a += hbm(br->partials)[2 * i];
+      b += hbm(br->partials)[2 * i + 1];
     }
     for (int o = 32; o > 0; o >>= 1) {
       a += __shfl_xor(a, o);
@@ -441,36 +428,50 @@ __global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restri
         c.c2 = 0.5 * br->fourpiG * mean;
         c.c1 = -br->fourpiG * mean * (b / a);
       }
-      *br->coef = c;
+      *hbm(br->coef) = c;
     }
   }
+}
 
-  // B-point DFT across j for each z
+// B-point DFT across j for each z; src(jj, z) is element z of pencil jj
+template <typename T, int M, int B, int Q, int NT, class Src>
+__device__ __forceinline__ void fb_dft_in(FbShared<T, M, B, Q>& sh, int tid, Src&& src) {
+  constexpr int NZ = M / Q;
+  constexpr int ZPT = (NZ + NT - 1) / NT;
+  using LT = Tile<B, 1, NZ, false>;  // parked pencils: element z of pencil k2
 #pragma unroll
   for (int zi = 0; zi < ZPT; ++zi) {
     const int z = tid + zi * NT;
     if (NZ % NT == 0 || z < NZ) {
       cplx<T> v[B];
 #pragma unroll
-      for (int jj = 0; jj < B; ++jj) v[jj] = base[(size_t)jj * NZ + z];
-      if (own0) {
-        double sx = 0.0;  // the k = 0 pencil is real: its imaginary parts are exact zeros
-#pragma unroll
-        for (int jj = 0; jj < B; ++jj) sx += (double)v[jj].x;
-        d0[kF32 ? z : 0] = sx;
-      }
+      for (int jj = 0; jj < B; ++jj) v[jj] = src(jj, z);
       Dft<B, -1, T>::run(v);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) tile[LT::at(z, k2)] = v[k2];
+      for (int k2 = 0; k2 < B; ++k2) sh.tile[LT::at(z, k2)] = v[k2];
     }
   }
-  __syncthreads();
+}
 
-  // wavefront-private padded z transforms, Green multiply and inverse: Q groups per tile area
-  const T* zt = static_cast<const T*>(br->zt);
-  const T L_ = (T)g.L;
-  const T sc = (T)scale;
+// wavefront-private padded z transforms, Green multiply and inverse: Q groups per tile area
+template <typename T, int M, int B, int Q, int WV>
+__device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbItem<T>& it, int tid) {
+  constexpr int PW = fb_pw<M, B, Q>();
+  constexpr int NTUP = fb_tuples<M, B, Q>();
+  constexpr int NZ = M / Q;
+  static_assert(Q * PW * NTUP == B, "groups must tile the B pencils");
+  using LT = Tile<B, 1, NZ, false>;
+  using LW = Tile<PW, 1, M, false>;  // one group's exchange layout inside its tuple's tile area
+  using RF = typename Fwd<M>::L;
+  using RI = typename Inv<M>::L;
+  using S0 = Stage<T, M, RF, 0, LW, 64, -1>;
+  using SL = Stage<T, M, RI, RI::n - 1, LW, 64, +1>;
+  constexpr int RIN = (S0::R % Q == 0) ? S0::R / Q : S0::R;
+  constexpr int ROUT = (SL::R % Q == 0) ? SL::R / Q : SL::R;
+  const bool own0 = it.own0;
+  gmem<const T>* zt = hbm(static_cast<const T*>(it.br->zt));
   const int wave = tid >> 6, lane = tid & 63;
+  cplx<T>* tile = sh.tile;
 #pragma unroll 1
   for (int tu = wave; tu < NTUP; tu += WV) {
     const int k0 = Q * PW * tu;  // first pencil of the tuple
@@ -490,19 +491,10 @@ __global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restri
       __builtin_amdgcn_sched_barrier(0);  // one transform at a time (register pressure)
       const int kq = k0 + q * PW;
       fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-          area, tw, lane, [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
+          area, sh.tw, lane, [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
           [&](int mz, int p, cplx<T>& v) {
             const int k2 = kq + p;
-            const ZRow<T> zr = zrow(zt, mz);
-            const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
-            T gk;
-            if (sasha) {
-              gk = (pzero[k2] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[k2] + kz2);
-            } else if (!pzero[k2]) {
-              gk = -(pa0[k2] + pe[k2] * (s2 + pik[k2] * ks)) * fast_rcp(pk2[k2] + kz2);
-            } else {
-              gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
-            }
+            const T gk = green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zrow(zt, mz));
             v.x *= gk;
             v.y *= gk;
           },
@@ -518,35 +510,78 @@ __global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restri
       });
     WaveSync::sync();  // this wavefront's next tuple starts from fresh reads
   }
-  __syncthreads();
+}
 
-  // inverse B-point DFT across k2, store
+// inverse B-point DFT across k2, store to the item's pencils in HBM
+template <typename T, int M, int B, int Q, int NT>
+__device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbItem<T>& it, int tid) {
+  constexpr int NZ = M / Q;
+  constexpr int ZPT = (NZ + NT - 1) / NT;
+  using LT = Tile<B, 1, NZ, false>;
+  const double scale = it.br->scale;
+  if (FbShared<T, M, B, Q>::kF32 && it.own0) {
+    // the real k = 0 pencil input in double, from the item's pencils (still in HBM), parked as a
+    // float pair (hi, lo) in the tile slots of pencil 0, whose transformed values are not used
+#pragma unroll
+    for (int zi = 0; zi < ZPT; ++zi) {
+      const int z = tid + zi * NT;
+      if (NZ % NT == 0 || z < NZ) {
+        double sx = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj) sx += (double)it.base[(size_t)jj * NZ + z].x;
+        const T hi = (T)sx;
+        sh.tile[LT::at(z, 0)] = mk<T>(hi, (T)(sx - (double)hi));
+      }
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int zi = 0; zi < ZPT; ++zi) {
     const int z = tid + zi * NT;
     if (NZ % NT == 0 || z < NZ) {
       cplx<T> v[B];
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) v[k2] = tile[LT::at(z, k2)];
-      if constexpr (kF32) {
-        if (own0) {
+      for (int k2 = 0; k2 < B; ++k2) v[k2] = sh.tile[LT::at(z, k2)];
+      if constexpr (FbShared<T, M, B, Q>::kF32) {
+        if (it.own0) {
           // the k = 0 pencil in double: the padded circular convolution
           // phi_0[z] = scale sum_z' h[(z - z') mod M] d0[z']
-          const double* h = br->k0h;
+          gmem<const double>* h = hbm(it.br->k0h);
           double acc = 0.0;
 #pragma unroll 2
           for (int zp = 0; zp < NZ; ++zp) {
             const int d = z - zp;
-            acc += h[d < 0 ? d + M : d] * d0[zp];
+            const cplx<T> d0 = sh.tile[LT::at(zp, 0)];
+            acc += h[d < 0 ? d + M : d] * ((double)d0.x + (double)d0.y);
           }
           v[0] = mk<T>((T)(acc * scale), T(0));
         }
       }
       Dft<B, +1, T>::run(v);
 #pragma unroll
-      for (int jj = 0; jj < B; ++jj) base[(size_t)jj * NZ + z] = v[jj];
+      for (int jj = 0; jj < B; ++jj) it.base[(size_t)jj * NZ + z] = v[jj];
     }
   }
+}
+
+template <typename T, int M, int B, int Q>
+__global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                            const cplx<T>* __restrict__ twm, int A) {
+  constexpr int WV = fb_waves<M, B, Q>();
+  constexpr int NT = 64 * WV;
+  __shared__ FbShared<T, M, B, Q> sh;
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const int tid = threadIdx.x;
+  const FbItem<T> it = fb_item<T, M, B, Q>(br, t);
+  load_twiddles<T, M, NT>(sh.tw, twm, tid);
+  fb_scalars(sh, it, A, tid);
+  fb_dft_in<T, M, B, Q, NT>(sh, tid,
+                                   [&](int jj, int z) { return it.base[(size_t)jj * (M / Q) + z]; });
+  __syncthreads();
+  fb_pencils<T, M, B, Q, WV>(sh, it, tid);
+  __syncthreads();
+  fb_dft_out<T, M, B, Q, NT>(sh, it, tid);
 }
 
 template <typename T>

@@ -15,12 +15,12 @@ hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int 
   const cplx<T>* t1 = static_cast<const cplx<T>*>(tw);
   (void)variant;
   if (kind == 1) {
-    const double2* t64 = static_cast<const double2*>(tw2);
-#define SBP_CASE(M_)                                                                                           \
-    if (len == M_) {                                                                                           \
-      if (q == 4) hipLaunchKernelGGL((k_fb<T, M_, B, 4>), grid, dim3(fb_threads<M_, B, 4>()), 0, st, ga, recs, t1, t64, a); \
-      else hipLaunchKernelGGL((k_fb<T, M_, B, 2>), grid, dim3(fb_threads<M_, B, 2>()), 0, st, ga, recs, t1, t64, a);       \
-      return hipGetLastError();                                                                                \
+    (void)tw2;
+#define SBP_CASE(M_)                \
+    if (len == M_) {                \
+      if (q == 4) hipLaunchKernelGGL((k_fb<T, M_, B, 4>), grid, dim3(fb_threads<M_, B, 4>()), 0, st, ga, recs, t1, a); \
+      else hipLaunchKernelGGL((k_fb<T, M_, B, 2>), grid, dim3(fb_threads<M_, B, 2>()), 0, st, ga, recs, t1, a);       \
+      return hipGetLastError();     \
     }
     SBP_CASE(32) SBP_CASE(64) SBP_CASE(128) SBP_CASE(256) SBP_CASE(512)
 #undef SBP_CASE

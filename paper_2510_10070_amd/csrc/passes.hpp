@@ -21,14 +21,57 @@ namespace sbp {
 template <typename T> struct ZRow {
   T s2, ks, kz2;
 };
-__device__ __forceinline__ ZRow<float> zrow(const float* t, int mz) {
-  const float4 v = reinterpret_cast<const float4*>(t)[mz];
+__device__ __forceinline__ ZRow<float> zrow(gmem<const float>* t, int mz) {
+  const float4 v = reinterpret_cast<gmem<const float4>*>(t)[mz];
   return {v.x, v.y, v.z};
 }
-__device__ __forceinline__ ZRow<double> zrow(const double* t, int mz) {
-  const double2 a = reinterpret_cast<const double2*>(t)[2 * mz];
+__device__ __forceinline__ ZRow<double> zrow(gmem<const double>* t, int mz) {
+  const double2 a = reinterpret_cast<gmem<const double2>*>(t)[2 * mz];
   const double b = t[4 * mz + 2];
   return {a.x, a.y, b};
+}
+
+// reciprocal: the hardware estimate in float (about 1 ulp), exact division in double
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+// Green's-function coefficients of one horizontal mode (Sect. 2.3, App. A; SASHA Sect. 2.2),
+// scaled by 4 pi G/(Nx Ny M): the multiplier at the z-table row {s2, ks, kz^2} is
+//   G = -(a0 + e (s2 + ik ks)) / (k^2 + kz^2),
+// and the one element whose denominator vanishes (k = 0, kz = 0) takes `zero` instead.
+//   VGF, k > 0:  a0 = 1 - exp(-kL), e = exp(-kL), ik = 1/k      (the stable form of G^L)
+//   VGF, k = 0:  a0 = 0, e = 1, ik = -L, zero = L^2/2           ((kz L sin kz L + cos kz L - 1)/kz^2)
+//   SASHA:       a0 = 1, e = ik = 0, zero = 0                    (-1/|k|^2, the mean mode dropped)
+template <typename T> struct ModeGreen {
+  T a0, e, ik, k2, zero;
+};
+template <typename T>
+__device__ __forceinline__ ModeGreen<T> mode_green(double kk2, bool k_zero, bool sasha, double L, double scale) {
+  ModeGreen<T> c;
+  c.k2 = (T)kk2;
+  c.zero = T(0);
+  if (sasha) {
+    c.a0 = (T)scale;
+    c.e = T(0);
+    c.ik = T(0);
+  } else if (!k_zero) {
+    const double k = sqrt(kk2);
+    c.a0 = (T)(-expm1(-k * L) * scale);
+    c.e = (T)(exp(-k * L) * scale);
+    c.ik = (T)(1.0 / k);
+  } else {
+    c.a0 = T(0);
+    c.e = (T)scale;
+    c.ik = (T)(-L);
+    c.zero = (T)(0.5 * L * L * scale);
+  }
+  return c;
+}
+template <typename T>
+__device__ __forceinline__ T green_at(T a0, T e, T ik, T k2, T zero, const ZRow<T>& zr) {
+  const T den = k2 + zr.kz2;
+  const T gk = -(a0 + e * (zr.s2 + ik * zr.ks)) * fast_rcp(den);
+  return den == T(0) ? zero : gk;
 }
 
 constexpr int kPassThreads = 256;
@@ -59,7 +102,7 @@ template <typename T, int M, int V> constexpr int z_pp() { return (kPassThreads 
 // ------------------------------------------------------------------------------------------
 // launch groups
 
-__device__ __forceinline__ int find_box(const int* __restrict__ starts, int n, int blk) {
+__device__ __forceinline__ int find_box(gmem<const int>* __restrict__ starts, int n, int blk) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -73,11 +116,12 @@ __device__ __forceinline__ int find_box(const int* __restrict__ starts, int n, i
 
 // locate this block's box and its tile index within the box (XCD-aware order over the launch)
 __device__ __forceinline__ const BoxRec* group_box(const GroupArgs& ga, const BoxRec* __restrict__ recs, int& tile) {
-  const int total = ga.starts[ga.n];
+  gmem<const int>* starts = hbm(ga.starts);
+  const int total = starts[ga.n];
   const int b = xcd_tile(blockIdx.x, total);
-  const int i = find_box(ga.starts, ga.n, b);
-  tile = b - ga.starts[i];
-  return recs + ga.box_ids[i];
+  const int i = find_box(starts, ga.n, b);
+  tile = b - starts[i];
+  return recs + hbm(ga.box_ids)[i];
 }
 
 // remap phase exp(-i 2 pi c) for c = my*(2x+1)*fy cycles, evaluated in double
@@ -115,9 +159,6 @@ struct YInterp {
   }
 };
 
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
-
 // ------------------------------------------------------------------------------------------
 // y forward: one block per (x plane, chunk of ZC consecutive z cells).  Consecutive z pairs
 // (z, z+1) are packed as one complex column, so one complex length-Ny FFT transforms two real
@@ -145,9 +186,9 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   const int x = t / nzc;
   const int z0 = (t - x * nzc) * ZC;
   const int hy = NY / 2;
-  const T* rho = static_cast<const T*>(br->rho);
-  cplx<T>* W = static_cast<cplx<T>*>(br->W);
-  double* partials = (REMAP && g.method == 1) ? br->partials : nullptr;  // SASHA sums only
+  gmem<const T>* rho = hbm(static_cast<const T*>(br->rho));
+  gmem<cplx<T>>* W = hbm(static_cast<cplx<T>*>(br->W));
+  gmem<double>* partials = (REMAP && g.method == 1) ? hbm(br->partials) : nullptr;  // SASHA sums only
 
   load_twiddles<T, NY, NT>(tw, twg, tid);
   if (REMAP) {
@@ -165,7 +206,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
       const int c = w % NB, y = w / NB;
       const int z = z0 + 2 * c;
       if (z < nz) {
-        const cplx<T> v = *reinterpret_cast<const cplx<T>*>(rho + ((size_t)x * NY + y) * nz + z);
+        const cplx<T> v = *reinterpret_cast<gmem<const cplx<T>>*>(rho + ((size_t)x * NY + y) * nz + z);
         const double za = -0.5 * g.lz + (z + 0.5) * dz;
         s0 += (double)v.x + (double)v.y;
         s1 += za * (double)v.x + (za + dz) * (double)v.y;
@@ -191,7 +232,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
     }
   }
 
-  const T* src = rho + (size_t)x * NY * nz + z0;
+  gmem<const T>* src = rho + (size_t)x * NY * nz + z0;
   const int zn = min(ZC, nz - z0);
   // linear remap: the periodic field at y_j is the lab field at y_j - shy (x + 1/2) cells
   const bool lin = REMAP && g.remap == 1;
@@ -201,7 +242,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
       tile, tw, tid,
       [&](int e, int c) {
         if (2 * c >= zn) return mk<T>(T(0), T(0));
-        auto ld = [&](int y) { return *reinterpret_cast<const cplx<T>*>(src + (size_t)y * nz + 2 * c); };
+        auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * c); };
         return lin ? yi.sample<T>(e, NY, ld) : ld(e);
       },
       [&](int e, int c, cplx<T> v) { tile[L::at(e, c)] = v; });
@@ -219,9 +260,9 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
       a = cmul<T>(a, p);
       b = cmul<T>(b, p);
     }
-    cplx<T>* dst = W + ((size_t)x * hy + ky) * nz + z0 + 2 * c;
+    gmem<cplx<T>>* dst = W + ((size_t)x * hy + ky) * nz + z0 + 2 * c;
     if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, b.x, b.y);
+      *reinterpret_cast<gmem<float4>*>(dst) = make_float4(a.x, a.y, b.x, b.y);
     } else {
       dst[0] = a;
       dst[1] = b;
@@ -252,8 +293,8 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   const int x = t / nzc;
   const int z0 = (t - x * nzc) * ZC;
   const int hy = NY / 2;
-  const cplx<T>* W = static_cast<const cplx<T>*>(br->W);
-  T* phi = static_cast<T*>(br->phi);
+  gmem<const cplx<T>>* W = hbm(static_cast<const cplx<T>*>(br->W));
+  gmem<T>* phi = hbm(static_cast<T*>(br->phi));
   const int zn = min(ZC, nz - z0);
 
   load_twiddles<T, NY, NT>(tw, twg, tid);
@@ -272,9 +313,9 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
     const int c = w % NB, ky = w / NB;
     cplx<T> a = mk<T>(T(0), T(0)), b = a;
     if (2 * c < zn) {
-      const cplx<T>* src = W + ((size_t)x * hy + ky) * nz + z0 + 2 * c;
+      gmem<const cplx<T>>* src = W + ((size_t)x * hy + ky) * nz + z0 + 2 * c;
       if constexpr (sizeof(T) == 4) {
-        const float4 q = *reinterpret_cast<const float4*>(src);
+        const float4 q = *reinterpret_cast<gmem<const float4>*>(src);
         a = mk<T>(q.x, q.y);
         b = mk<T>(q.z, q.w);
       } else {
@@ -298,11 +339,11 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   const bool sasha = REMAP && g.method == 1;
   double c2 = 0.0, c1 = 0.0;
   if (sasha) {
-    c2 = br->coef->c2;
-    c1 = br->coef->c1;
+    c2 = hbm(br->coef)->c2;
+    c1 = hbm(br->coef)->c1;
   }
   const double dz = g.lz / nz;
-  T* dst = phi + (size_t)x * NY * nz + z0;
+  gmem<T>* dst = phi + (size_t)x * NY * nz + z0;
   auto store = [&](int e, int c, cplx<T> v) {
     if (2 * c < zn) {
       if (sasha) {
@@ -311,7 +352,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
         v.x = (T)((double)v.x + (c2 * za + c1) * za);
         v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
       }
-      *reinterpret_cast<cplx<T>*>(dst + (size_t)e * nz + 2 * c) = v;
+      *reinterpret_cast<gmem<cplx<T>>*>(dst + (size_t)e * nz + 2 * c) = v;
     }
   };
   if (REMAP && g.remap == 1) {
@@ -355,7 +396,7 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
   const int z0 = (t - my * nzc) * ZC;
   const int zn = min(ZC, nz - z0);
   const size_t row = (size_t)hy * nz;
-  cplx<T>* base = static_cast<cplx<T>*>(br->W) + (size_t)my * nz + z0;
+  gmem<cplx<T>>* base = hbm(static_cast<cplx<T>*>(br->W)) + (size_t)my * nz + z0;
   load_twiddles<T, NX, NT>(tw, twg, tid);
   fft_run<T, NX, typename Fwd<NX>::L, L, NT, D, false, false>(
       buf, tw, tid, [&](int e, int c) { return c < zn ? base[e * row + c] : mk<T>(T(0), T(0)); },
@@ -394,8 +435,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   constexpr int XS = lds_slots(PW * M);
   __shared__ cplx<T> xbuf[WV * XS];
   __shared__ cplx<T> tw[M];
-  __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW];
-  __shared__ int pzero[WV][PPW];
+  __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW], psp[WV][PPW];
   // block-0 work before the wavefront transforms borrows xbuf (SASHA reduction, then the double
   // k = 0 exchange tile of float plans)
   static_assert(lds_slots(M) * 16 <= WV * XS * (int)sizeof(cplx<T>), "k = 0 tile must fit");
@@ -411,8 +451,8 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   const int nz = g.nz;
   const bool sasha = g.method == 1;
   const double scale = br->scale;
-  cplx<T>* W = static_cast<cplx<T>*>(br->W);
-  const T* zt = static_cast<const T*>(br->zt);
+  gmem<cplx<T>>* W = hbm(static_cast<cplx<T>*>(br->W));
+  gmem<const T>* zt = hbm(static_cast<const T*>(br->zt));
   const int pw0 = (t * WV + wave) * PPW;  // first pencil of this wavefront
 
   load_twiddles<T, M, NT>(tw, twg, tid);
@@ -423,20 +463,12 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
     const double two_pi = 6.283185307179586476925286766559;
     const double Ky = (two_pi / g.ly) * my;
     const double kx = (two_pi / g.lx) * sx + br->s * Ky;
-    const double k2 = kx * kx + Ky * Ky;
-    const double k = sqrt(k2);
-    const int zero = (mx == 0 && my == 0);
-    pzero[wave][lane] = zero;
-    pk2[wave][lane] = (T)k2;
-    if (!zero && !sasha) {
-      pa0[wave][lane] = (T)(-expm1(-k * g.L) * scale);
-      pe[wave][lane] = (T)(exp(-k * g.L) * scale);
-      pik[wave][lane] = (T)(1.0 / k);
-    } else {
-      pa0[wave][lane] = T(0);
-      pe[wave][lane] = T(0);
-      pik[wave][lane] = T(0);
-    }
+    const ModeGreen<T> c = mode_green<T>(kx * kx + Ky * Ky, mx == 0 && my == 0, sasha, g.L, scale);
+    pa0[wave][lane] = c.a0;
+    pe[wave][lane] = c.e;
+    pik[wave][lane] = c.ik;
+    pk2[wave][lane] = c.k2;
+    psp[wave][lane] = c.zero;
   }
 
   // SASHA: <rho> and the centre of mass from the y-pass partial sums (fixed order)
@@ -444,8 +476,8 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
     double* red = reinterpret_cast<double*>(xbuf);
     double a = 0.0, b = 0.0;
     for (int i = tid; i < br->npartials; i += NT) {
-      a += br->partials[2 * i];
-      b += br->partials[2 * i + 1];
+      a += hbm(br->partials)[2 * i];
+      b += hbm(br->partials)[2 * i + 1];
     }
     red[tid] = a;
     red[NT + tid] = b;
@@ -467,7 +499,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
         c.c2 = 0.5 * br->fourpiG * mean;
         c.c1 = -br->fourpiG * mean * (s1 / s0);
       }
-      *br->coef = c;
+      *hbm(br->coef) = c;
     }
   }
   __syncthreads();  // twiddles loaded; reduction scratch free
@@ -478,10 +510,10 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
     if (t == 0) {
       using L1 = Tile<1, 1, M, false>;
       double2* dbuf = reinterpret_cast<double2*>(xbuf);
-      float2* w0 = reinterpret_cast<float2*>(W);
-      const double* z64s2 = br->zt64[0];
-      const double* z64ks = br->zt64[1];
-      const double* z64kz2 = br->zt64[2];
+      gmem<float2>* w0 = reinterpret_cast<gmem<float2>*>(W);
+      gmem<const double>* z64s2 = hbm(br->zt64[0]);
+      gmem<const double>* z64ks = hbm(br->zt64[1]);
+      gmem<const double>* z64kz2 = hbm(br->zt64[2]);
       fft_fwd_op_inv<double, M, L1, NT, 0, Q>(
           dbuf, tw64, tid,
           [&](int e, int) { return e < nz ? make_double2((double)w0[e].x, (double)w0[e].y) : make_double2(0.0, 0.0); },
@@ -502,8 +534,6 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
     }
   }
 
-  const T L_ = (T)g.L;
-  const T sc = (T)scale;
   cplx<T>* xw = xbuf + wave * XS;
 #pragma unroll 1
   for (int g0 = 0; g0 < PPW; g0 += PW) {
@@ -516,16 +546,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
         },
         [&](int mz, int p, cplx<T>& v) {
           const int i = g0 + p;
-          const ZRow<T> zr = zrow(zt, mz);
-          const T s2 = zr.s2, ks = zr.ks, kz2 = zr.kz2;
-          T gk;
-          if (sasha) {
-            gk = (pzero[wave][i] && mz == 0) ? T(0) : -sc * fast_rcp(pk2[wave][i] + kz2);
-          } else if (!pzero[wave][i]) {
-            gk = -(pa0[wave][i] + pe[wave][i] * (s2 + pik[wave][i] * ks)) * fast_rcp(pk2[wave][i] + kz2);
-          } else {
-            gk = sc * (mz == 0 ? T(0.5) * L_ * L_ : (L_ * ks - s2) / kz2);
-          }
+          const T gk = green_at(pa0[wave][i], pe[wave][i], pik[wave][i], pk2[wave][i], psp[wave][i], zrow(zt, mz));
           v.x *= gk;
           v.y *= gk;
         },

@@ -45,6 +45,18 @@ struct BoxRec {
   const double* k0h;     // k = 0 pencil in real space: h[n] = sum_m G(0, kz_m) cos(2 pi m n/M)
 };
 
+// Pointers held in the records and launch arguments address device global memory.  Kernels
+// access that memory through gmem<T>* (from hbm()) so that the accesses compile to global
+// rather than flat instructions: a flat access also counts against the LDS counter, so every
+// LDS wait behind an outstanding flat load or store would wait for HBM as well.
+// (The host pass of the same source, which only checks kernel bodies, sees plain types.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using gmem = __attribute__((address_space(1))) T;
+#else
+template <class T> using gmem = T;
+#endif
+template <class T> __device__ __forceinline__ gmem<T>* hbm(T* p) { return (gmem<T>*)p; }
+
 // A launch serves a group of boxes with the same kernel shape.
 struct GroupArgs {
   const int* box_ids;  // boxes of the group (indices into the BoxRec array)
