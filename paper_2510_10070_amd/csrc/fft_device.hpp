@@ -179,6 +179,14 @@ template <int... Rs> struct RList {
 };
 template <int N> struct Fwd;
 template <int N> struct Inv;
+// the inverse schedule is the forward one reversed: one stage-major table serves both when the
+// radix list reads the same both ways
+template <class A, class B> constexpr bool same_schedule() {
+  if (A::n != B::n) return false;
+  for (int i = 0; i < A::n; ++i)
+    if (A::r[i] != B::r[i]) return false;
+  return true;
+}
 template <> struct Fwd<8> { using L = RList<8>; };
 template <> struct Inv<8> { using L = RList<8>; };
 template <> struct Fwd<12> { using L = RList<4, 3>; };
@@ -218,6 +226,15 @@ template <int NB_, int LD_, int BS_, bool BFAST_> struct Tile {
   static constexpr bool BFAST = BFAST_;
   static __device__ __forceinline__ int logical(int j, int b) { return j * LD + b * BS; }
   static __device__ __forceinline__ int at(int j, int b) { return pad8(j * LD + b * BS); }
+};
+
+// Stage-major twiddle table of a schedule: stage S (Ns = product of the earlier radices, radix
+// R) keeps exp(-2 pi i k r/(Ns R)), r = 1 .. R-1, k < Ns, at slot Ns - 1 + (r - 1) Ns + k, so
+// N - 1 slots in all.  The lanes of a stage then read consecutive slots (no LDS bank
+// conflicts, where the strided plain table has up to 8-way conflicts), and the r offsets are
+// compile-time constants.
+template <typename T> struct TwS {
+  const cplx<T>* p;
 };
 
 // One Stockham stage of schedule RL for a tile L processed by NT threads.
@@ -277,7 +294,10 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
     else
       return pad8(a + r * C);
   }
-  static __device__ __forceinline__ void twiddle_dft(cplx<T> (&v)[PER][R], const cplx<T>* tw, int tid) {
+  // tw: the plain table exp(-2 pi i m/N), m < N (a pointer), or the stage-major table of this
+  // schedule (TwS)
+  template <class TW>
+  static __device__ __forceinline__ void twiddle_dft(cplx<T> (&v)[PER][R], TW tw, int tid) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       int j, b;
@@ -286,7 +306,11 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
           const int k = j % NS;
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            const cplx<T> t = tw[k * r * (N / (NS * R))];
+            cplx<T> t;
+            if constexpr (std::is_pointer_v<TW>)
+              t = tw[k * r * (N / (NS * R))];
+            else
+              t = tw.p[NS - 1 + (r - 1) * NS + k];
             v[p][r] = D < 0 ? cmul<T>(v[p][r], t) : cmulc<T>(v[p][r], t);
           }
         }
@@ -361,8 +385,8 @@ struct WaveSync {
 // next write to it.  On return without DST_LDS the last stage has read `buf`: the caller must
 // barrier before writing it again; with DST_LDS the caller must barrier before reading it.
 template <typename T, int N, class RL, class L, int NT, int D, bool SRC_LDS, bool DST_LDS, int S = 0, int Q = 1,
-          class Sy = BlockSync, class Src, class Dst>
-__device__ __forceinline__ void fft_run(cplx<T>* buf, const cplx<T>* tw, int tid, Src&& src, Dst&& dst) {
+          class Sy = BlockSync, class TW, class Src, class Dst>
+__device__ __forceinline__ void fft_run(cplx<T>* buf, TW tw, int tid, Src&& src, Dst&& dst) {
   using St = Stage<T, N, RL, S, L, NT, D>;
   constexpr bool LAST = S == RL::n - 1;
   cplx<T> v[St::PER][St::R];
@@ -386,12 +410,32 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, const cplx<T>* tw, int tid
 
 // Forward transform, pointwise op, inverse transform, with the hand-off between the last
 // forward stage and the first inverse stage kept in registers.
-//   src(elem, b) -> cplx (forward inputs), op(elem, b, cplx&) on spectrum values,
-//   dst(elem, b, v) (inverse outputs).
+//   src(elem, b) -> cplx (forward inputs), op(elem, b, cplx&) on spectrum values (op(elem, b,
+//   cplx&, slot) also gets the register slot, which is fixed per thread and element, see
+//   spectrum_slot), dst(elem, b, v) (inverse outputs); twf, twi: twiddles of the forward and of the inverse
+//   schedule (the same plain table, or each schedule's stage-major table).
 // Q > 1 (zero padding by Q): forward inputs at or above N/Q are zero and inverse outputs at or
 // above N/Q are discarded; both are dropped at compile time where the radix allows.
-template <typename T, int N, class L, int NT, int S, int Q = 1, class Sy = BlockSync, class Src, class Op, class Dst>
-__device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, int tid, Src&& src, Op&& op,
+// The spectrum element that thread tid holds at register slot i of the forward-inverse
+// hand-off in fft_fwd_op_inv (-1 where the slot is unused): the op's arguments per slot are the
+// same on every call, so per-element constants can be fetched once per thread.
+template <typename T, int N, class L, int NT>
+__device__ __forceinline__ int spectrum_slot(int tid, int i) {
+  using RF = typename Fwd<N>::L;
+  using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
+  int j, b;
+  if (!Sf::item(tid, i / Sf::R, j, b)) return -1;
+  return j + (i % Sf::R) * Sf::NBF;
+}
+template <typename T, int N, class L, int NT> constexpr int spectrum_slots() {
+  using RF = typename Fwd<N>::L;
+  using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
+  return Sf::PER * Sf::R;
+}
+
+template <typename T, int N, class L, int NT, int S, int Q = 1, class Sy = BlockSync, class TWF, class TWI,
+          class Src, class Op, class Dst>
+__device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, TWF twf, TWI twi, int tid, Src&& src, Op&& op,
                                                Dst&& dst) {
   using RF = typename Fwd<N>::L;
   using RI = typename Inv<N>::L;
@@ -406,10 +450,10 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, 
       St::read_lds(v, buf, tid);
       Sy::sync();
     }
-    St::twiddle_dft(v, tw, tid);
+    St::twiddle_dft(v, twf, tid);
     St::write_lds(v, buf, tid);
     Sy::sync();
-    fft_fwd_op_inv<T, N, L, NT, S + 1, Q, Sy>(buf, tw, tid, src, op, dst);
+    fft_fwd_op_inv<T, N, L, NT, S + 1, Q, Sy>(buf, twf, twi, tid, src, op, dst);
   } else {
     using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
     using Si = Stage<T, N, RI, 0, L, NT, +1>;
@@ -421,32 +465,53 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, const cplx<T>* tw, 
       Sf::read_lds(v, buf, tid);
       Sy::sync();
     }
-    Sf::twiddle_dft(v, tw, tid);
+    Sf::twiddle_dft(v, twf, tid);
     // last forward stage: outputs j + r*NBF (base = j since j < NS = NBF)
 #pragma unroll
     for (int p = 0; p < Sf::PER; ++p) {
       int j, b;
       if (Sf::item(tid, p, j, b)) {
 #pragma unroll
-        for (int r = 0; r < Sf::R; ++r) op(j + r * Sf::NBF, b, v[p][r]);
+        for (int r = 0; r < Sf::R; ++r) {
+          // an op taking a fourth argument also gets the register slot p R + r
+          if constexpr (std::is_invocable_v<Op&, int, int, cplx<T>&, int>)
+            op(j + r * Sf::NBF, b, v[p][r], p * Sf::R + r);
+          else
+            op(j + r * Sf::NBF, b, v[p][r]);
+        }
       }
     }
     // first inverse stage on the same registers (Ns = 1: no twiddles)
-    Si::twiddle_dft(v, tw, tid);
+    Si::twiddle_dft(v, twi, tid);
     if constexpr (RI::n == 1) {
       Si::template write_fn<(Si::R % Q == 0) ? Si::R / Q : Si::R>(v, tid, dst);
     } else {
       Si::write_lds(v, buf, tid);
       Sy::sync();
-      fft_run<T, N, RI, L, NT, +1, false, false, 1, Q, Sy>(buf, tw, tid, src, dst);
+      fft_run<T, N, RI, L, NT, +1, false, false, 1, Q, Sy>(buf, twi, tid, src, dst);
     }
   }
 }
 
-// copy the N-entry twiddle table into LDS
-template <typename T, int N, int NT>
+// build the stage-major table of schedule RL (N - 1 slots) in LDS from the plain table
+template <typename T, int N, class RL, int NT>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src, int tid) {
-  for (int i = tid; i < N; i += NT) dst[i] = src[i];
+  for (int i = tid; i < N - 1; i += NT) {
+    int ns = 1, s = 0;
+#pragma unroll
+    for (int q = 1; q < RL::n; ++q)
+      if (i >= RL::ns(q) - 1) {
+        ns = RL::ns(q);
+        s = q;
+      }
+    int R = 1;
+#pragma unroll
+    for (int q = 0; q < RL::n; ++q)
+      if (q == s) R = RL::r[q];
+    const int rem = i - (ns - 1);
+    const int r = rem / ns + 1, k = rem - (r - 1) * ns;
+    dst[i] = src[k * r * (N / (ns * R))];
+  }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each XCD
@@ -456,16 +521,6 @@ __device__ __forceinline__ int xcd_tile(int b, int T) {
   const int q = T >> 3, r = T & 7;
   const int xcd = b & 7, slot = b >> 3;
   return xcd * q + (xcd < r ? xcd : r) + slot;
-}
-
-// Legacy in-place transform of a full LDS tile (both ends in LDS): used by small helpers.
-template <typename T, int N, class L, int NT, int D>
-__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
-  using RL = typename Fwd<N>::L;
-  fft_run<T, N, RL, L, NT, D, true, true>(
-      buf, tw, tid, [&](int e, int b) { return buf[L::at(e, b)]; },
-      [&](int e, int b, cplx<T> v) { buf[L::at(e, b)] = v; });
-  __syncthreads();
 }
 
 }  // namespace sbp

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   const bool sasha = g.method == 1;
   const double dz = g.lz / nz;
   cplx<T>* mytile = tile + sub * SLOTS;
-  load_twiddles<T, NY, NT>(tw, twy, tid);
+  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twy, tid);
 
   PlanePhase pp[POS];
 #pragma unroll
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
     YInterp yi;
     if (lin) yi.init(-br->shy * (x + 0.5), NY);
     fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true>(
-        mytile, tw, stid,
+        mytile, TwS<T>{tw}, stid,
         [&](int e, int c) {
           cplx<T> v = mk<T>(T(0), T(0));
           if (2 * c < zn) {
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   gmem<T>* phi = hbm(static_cast<T*>(br->phi));
   const int nx = g.nx;
   cplx<T>* mytile = tile + sub * SLOTS;
-  load_twiddles<T, NY, NT>(tw, twy, tid);
+  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twy, tid);
 
   cplx<T> acc[A][POS][2];
   PlanePhase pp[POS];
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
       YInterp yi;
       yi.init(br->shy * (x + 0.5), NY);
       fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true>(
-          mytile, tw, stid, [&](int e, int c) { return mytile[L::at(e, c)]; },
+          mytile, TwS<T>{tw}, stid, [&](int e, int c) { return mytile[L::at(e, c)]; },
           [&](int e, int c, cplx<T> v) { mytile[L::at(e, c)] = v; });
       __syncthreads();
       for (int w = stid; w < NY * NB; w += TNT) {
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
       }
     } else {
       fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
-          mytile, tw, stid, [&](int e, int c) { return mytile[L::at(e, c)]; }, store);
+          mytile, TwS<T>{tw}, stid, [&](int e, int c) { return mytile[L::at(e, c)]; }, store);
     }
     __syncthreads();  // the tiles are rebuilt for the next planes
   }
@@ -364,7 +364,9 @@ template <typename T, int M, int B, int Q> struct FbShared {
   static constexpr int NZ = M / Q;
   static constexpr bool kF32 = std::is_same<T, float>::value;
   cplx<T> tile[lds_slots(B * NZ)];
-  cplx<T> tw[M];
+  // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
+  static constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
+  cplx<T> tw[kOneTw ? M : 2 * M];
   T pa0[B], pe[B], pik[B], pk2[B], psp[B];  // Green's-function coefficients of the B modes
 };
 
@@ -469,9 +471,19 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
   constexpr int RIN = (S0::R % Q == 0) ? S0::R / Q : S0::R;
   constexpr int ROUT = (SL::R % Q == 0) ? SL::R / Q : SL::R;
   const bool own0 = it.own0;
-  gmem<const T>* zt = hbm(static_cast<const T*>(it.br->zt));
   const int wave = tid >> 6, lane = tid & 63;
   cplx<T>* tile = sh.tile;
+  // the z-table rows of this lane's spectrum elements: the same for every pencil it transforms
+  constexpr int NSL = spectrum_slots<T, M, LW, 64>();
+  ZRow<T> zr[NSL];
+  {
+    gmem<const T>* zt = hbm(static_cast<const T*>(it.br->zt));
+#pragma unroll
+    for (int i = 0; i < NSL; ++i) {
+      const int mz = spectrum_slot<T, M, LW, 64>(lane, i);
+      zr[i] = zrow(zt, mz < 0 ? 0 : mz);
+    }
+  }
 #pragma unroll 1
   for (int tu = wave; tu < NTUP; tu += WV) {
     const int k0 = Q * PW * tu;  // first pencil of the tuple
@@ -491,10 +503,11 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
       __builtin_amdgcn_sched_barrier(0);  // one transform at a time (register pressure)
       const int kq = k0 + q * PW;
       fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-          area, sh.tw, lane, [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
-          [&](int mz, int p, cplx<T>& v) {
+          area, TwS<T>{sh.tw}, TwS<T>{sh.tw + (FbShared<T, M, B, Q>::kOneTw ? 0 : M)}, lane,
+          [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
+          [&](int, int p, cplx<T>& v, int i) {
             const int k2 = kq + p;
-            const T gk = green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zrow(zt, mz));
+            const T gk = green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zr[i]);
             v.x *= gk;
             v.y *= gk;
           },
@@ -574,7 +587,8 @@ __global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restri
   const BoxRec* br = group_box(ga, recs, t);
   const int tid = threadIdx.x;
   const FbItem<T> it = fb_item<T, M, B, Q>(br, t);
-  load_twiddles<T, M, NT>(sh.tw, twm, tid);
+  load_twiddles<T, M, typename Fwd<M>::L, NT>(sh.tw, twm, tid);
+  if constexpr (!FbShared<T, M, B, Q>::kOneTw) load_twiddles<T, M, typename Inv<M>::L, NT>(sh.tw + M, twm, tid);
   fb_scalars(sh, it, A, tid);
   fb_dft_in<T, M, B, Q, NT>(sh, tid,
                                    [&](int jj, int z) { return it.base[(size_t)jj * (M / Q) + z]; });

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   gmem<cplx<T>>* W = hbm(static_cast<cplx<T>*>(br->W));
   gmem<double>* partials = (REMAP && g.method == 1) ? hbm(br->partials) : nullptr;  // SASHA sums only
 
-  load_twiddles<T, NY, NT>(tw, twg, tid);
+  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twg, tid);
   if (REMAP) {
     const double fy = br->fy;
     for (int my = tid; my < hy; my += NT) {
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   YInterp yi;
   if (lin) yi.init(-br->shy * (x + 0.5), NY);
   fft_run<T, NY, typename Fwd<NY>::L, L, NT, -1, false, true>(
-      tile, tw, tid,
+      tile, TwS<T>{tw}, tid,
       [&](int e, int c) {
         if (2 * c >= zn) return mk<T>(T(0), T(0));
         auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * c); };
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   gmem<T>* phi = hbm(static_cast<T*>(br->phi));
   const int zn = min(ZC, nz - z0);
 
-  load_twiddles<T, NY, NT>(tw, twg, tid);
+  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twg, tid);
   if (REMAP) {
     const double fy = br->fy;
     for (int my = tid; my < hy; my += NT) {
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
     YInterp yi;
     yi.init(br->shy * (x + 0.5), NY);
     fft_run<T, NY, typename Fwd<NY>::L, L, NT, +1, true, true>(
-        tile, tw, tid, [&](int e, int c) { return tile[L::at(e, c)]; },
+        tile, TwS<T>{tw}, tid, [&](int e, int c) { return tile[L::at(e, c)]; },
         [&](int e, int c, cplx<T> v) { tile[L::at(e, c)] = v; });
     __syncthreads();
     for (int w = tid; w < NY * NB; w += NT) {
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
     }
   } else {
     fft_run<T, NY, typename Fwd<NY>::L, L, NT, +1, true, false>(
-        tile, tw, tid, [&](int e, int c) { return tile[L::at(e, c)]; }, store);
+        tile, TwS<T>{tw}, tid, [&](int e, int c) { return tile[L::at(e, c)]; }, store);
   }
 }
 
@@ -397,9 +397,9 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
   const int zn = min(ZC, nz - z0);
   const size_t row = (size_t)hy * nz;
   gmem<cplx<T>>* base = hbm(static_cast<cplx<T>*>(br->W)) + (size_t)my * nz + z0;
-  load_twiddles<T, NX, NT>(tw, twg, tid);
+  load_twiddles<T, NX, typename Fwd<NX>::L, NT>(tw, twg, tid);
   fft_run<T, NX, typename Fwd<NX>::L, L, NT, D, false, false>(
-      buf, tw, tid, [&](int e, int c) { return c < zn ? base[e * row + c] : mk<T>(T(0), T(0)); },
+      buf, TwS<T>{tw}, tid, [&](int e, int c) { return c < zn ? base[e * row + c] : mk<T>(T(0), T(0)); },
       [&](int e, int c, cplx<T> v) {
         if (c < zn) base[e * row + c] = v;
       });
@@ -434,7 +434,9 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   using LW = Tile<PW, 1, M, false>;
   constexpr int XS = lds_slots(PW * M);
   __shared__ cplx<T> xbuf[WV * XS];
-  __shared__ cplx<T> tw[M];
+  // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
+  constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
+  __shared__ cplx<T> tw[kOneTw ? M : 2 * M];
   __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW], psp[WV][PPW];
   // block-0 work before the wavefront transforms borrows xbuf (SASHA reduction, then the double
   // k = 0 exchange tile of float plans)
@@ -455,7 +457,8 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   gmem<const T>* zt = hbm(static_cast<const T*>(br->zt));
   const int pw0 = (t * WV + wave) * PPW;  // first pencil of this wavefront
 
-  load_twiddles<T, M, NT>(tw, twg, tid);
+  load_twiddles<T, M, typename Fwd<M>::L, NT>(tw, twg, tid);
+  if constexpr (!kOneTw) load_twiddles<T, M, typename Inv<M>::L, NT>(tw + M, twg, tid);
   if (lane < PPW) {
     const int q = min(pw0 + lane, np - 1);
     const int mx = q / hy, my = q - mx * hy;
@@ -515,7 +518,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
       gmem<const double>* z64ks = hbm(br->zt64[1]);
       gmem<const double>* z64kz2 = hbm(br->zt64[2]);
       fft_fwd_op_inv<double, M, L1, NT, 0, Q>(
-          dbuf, tw64, tid,
+          dbuf, tw64, tw64, tid,
           [&](int e, int) { return e < nz ? make_double2((double)w0[e].x, (double)w0[e].y) : make_double2(0.0, 0.0); },
           [&](int mz, int, double2& v) {
             double gk;
@@ -535,18 +538,26 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   }
 
   cplx<T>* xw = xbuf + wave * XS;
+  // the z-table rows of this lane's spectrum elements: the same for every pencil it transforms
+  constexpr int NSL = spectrum_slots<T, M, LW, 64>();
+  ZRow<T> zr[NSL];
+#pragma unroll
+  for (int i = 0; i < NSL; ++i) {
+    const int mz = spectrum_slot<T, M, LW, 64>(lane, i);
+    zr[i] = zrow(zt, mz < 0 ? 0 : mz);
+  }
 #pragma unroll 1
   for (int g0 = 0; g0 < PPW; g0 += PW) {
     if (pw0 + g0 >= np) break;  // uniform across the wavefront
     fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-        xw, tw, lane,
+        xw, TwS<T>{tw}, TwS<T>{tw + (kOneTw ? 0 : M)}, lane,
         [&](int e, int p) {
           const int q = pw0 + g0 + p;
           return (e < nz && q < np && !(own0 && q == 0)) ? W[(size_t)q * nz + e] : mk<T>(T(0), T(0));
         },
-        [&](int mz, int p, cplx<T>& v) {
+        [&](int, int p, cplx<T>& v, int sl) {
           const int i = g0 + p;
-          const T gk = green_at(pa0[wave][i], pe[wave][i], pik[wave][i], pk2[wave][i], psp[wave][i], zrow(zt, mz));
+          const T gk = green_at(pa0[wave][i], pe[wave][i], pik[wave][i], pk2[wave][i], psp[wave][i], zr[sl]);
           v.x *= gk;
           v.y *= gk;
         },
