@@ -235,6 +235,14 @@ template <int NB_, int LD_, int BS_, bool BFAST_> struct Tile {
 // compile-time constants.
 template <typename T> struct TwS {
   const cplx<T>* p;
+  __device__ __forceinline__ cplx<T> at(int i) const { return p[i]; }
+};
+// The same table kept in the spare slots of a pad8 tile (slot 9 i + 8 holds entry i): a tile of
+// 8 (N - 1) + 8 logical elements or more has room for it, and its stride-9 reads are
+// conflict-free as well.
+template <typename T> struct TwH {
+  const cplx<T>* tile;
+  __device__ __forceinline__ cplx<T> at(int i) const { return tile[9 * i + 8]; }
 };
 
 // One Stockham stage of schedule RL for a tile L processed by NT threads.
@@ -310,7 +318,7 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
             if constexpr (std::is_pointer_v<TW>)
               t = tw[k * r * (N / (NS * R))];
             else
-              t = tw.p[NS - 1 + (r - 1) * NS + k];
+              t = tw.at(NS - 1 + (r - 1) * NS + k);
             v[p][r] = D < 0 ? cmul<T>(v[p][r], t) : cmulc<T>(v[p][r], t);
           }
         }
@@ -493,8 +501,9 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, TWF twf, TWI twi, i
   }
 }
 
-// build the stage-major table of schedule RL (N - 1 slots) in LDS from the plain table
-template <typename T, int N, class RL, int NT>
+// build the stage-major table of schedule RL (N - 1 entries) in LDS from the plain table; entry
+// i goes to dst[STRIDE i + OFF] (STRIDE 9, OFF 8: the spare slots of a pad8 tile)
+template <typename T, int N, class RL, int NT, int STRIDE = 1, int OFF = 0>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src, int tid) {
   for (int i = tid; i < N - 1; i += NT) {
     int ns = 1, s = 0;
@@ -510,7 +519,7 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __res
       if (q == s) R = RL::r[q];
     const int rem = i - (ns - 1);
     const int r = rem / ns + 1, k = rem - (r - 1) * ns;
-    dst[i] = src[k * r * (N / (ns * R))];
+    dst[STRIDE * i + OFF] = src[k * r * (N / (ns * R))];
   }
 }
 

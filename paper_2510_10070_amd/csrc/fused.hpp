@@ -359,16 +359,39 @@ template <int M, int B, int Q> constexpr int fb_tuples() { return B / (Q * fb_pw
 template <int M, int B, int Q> constexpr int fb_waves() { return fb_tuples<M, B, Q>() < 4 ? fb_tuples<M, B, Q>() : 4; }
 template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves<M, B, Q>(); }
 
+// Twiddles: the stage-major table of the forward schedule of M, then that of the inverse one if
+// it differs.  When one table serves both and the tile's spare pad8 slots can hold it, it lives
+// there (TwH): the block then fits four to a CU in float.
+template <int M, int B, int Q> constexpr bool fb_tw_in_holes() {
+  return same_schedule<typename Fwd<M>::L, typename Inv<M>::L>() && B * (M / Q) >= 8 * (M - 1) + 8;
+}
+template <typename T, int M, int B, int Q> constexpr int fb_waves_per_eu() {
+  return (sizeof(T) == 4 && fb_tw_in_holes<M, B, Q>()) ? 4 : 1;
+}
+
 template <typename T, int M, int B, int Q> struct FbShared {
   static constexpr int PW = fb_pw<M, B, Q>();
   static constexpr int NZ = M / Q;
   static constexpr bool kF32 = std::is_same<T, float>::value;
-  cplx<T> tile[lds_slots(B * NZ)];
-  // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
   static constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
-  cplx<T> tw[kOneTw ? M : 2 * M];
+  static constexpr bool kHoles = fb_tw_in_holes<M, B, Q>();
+  cplx<T> tile[lds_slots(B * NZ)];
+  cplx<T> tw[kHoles ? 1 : kOneTw ? M : 2 * M];
   T pa0[B], pe[B], pik[B], pk2[B], psp[B];  // Green's-function coefficients of the B modes
 };
+
+template <typename T, int M, int B, int Q> __device__ __forceinline__ auto fb_twf(const FbShared<T, M, B, Q>& sh) {
+  if constexpr (FbShared<T, M, B, Q>::kHoles)
+    return TwH<T>{sh.tile};
+  else
+    return TwS<T>{sh.tw};
+}
+template <typename T, int M, int B, int Q> __device__ __forceinline__ auto fb_twi(const FbShared<T, M, B, Q>& sh) {
+  if constexpr (FbShared<T, M, B, Q>::kHoles)
+    return TwH<T>{sh.tile};
+  else
+    return TwS<T>{sh.tw + (FbShared<T, M, B, Q>::kOneTw ? 0 : M)};
+}
 
 // one (k1, my) item of a box
 template <typename T> struct FbItem {
@@ -503,8 +526,7 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
       __builtin_amdgcn_sched_barrier(0);  // one transform at a time (register pressure)
       const int kq = k0 + q * PW;
       fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-          area, TwS<T>{sh.tw}, TwS<T>{sh.tw + (FbShared<T, M, B, Q>::kOneTw ? 0 : M)}, lane,
-          [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
+          area, fb_twf(sh), fb_twi(sh), lane, [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
           [&](int, int p, cplx<T>& v, int i) {
             const int k2 = kq + p;
             const T gk = green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zr[i]);
@@ -578,7 +600,7 @@ __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbIte
 }
 
 template <typename T, int M, int B, int Q>
-__global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_per_eu<T, M, B, Q>()))) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
                                             const cplx<T>* __restrict__ twm, int A) {
   constexpr int WV = fb_waves<M, B, Q>();
   constexpr int NT = 64 * WV;
@@ -587,8 +609,12 @@ __global__ __launch_bounds__(256) void k_fb(GroupArgs ga, const BoxRec* __restri
   const BoxRec* br = group_box(ga, recs, t);
   const int tid = threadIdx.x;
   const FbItem<T> it = fb_item<T, M, B, Q>(br, t);
-  load_twiddles<T, M, typename Fwd<M>::L, NT>(sh.tw, twm, tid);
-  if constexpr (!FbShared<T, M, B, Q>::kOneTw) load_twiddles<T, M, typename Inv<M>::L, NT>(sh.tw + M, twm, tid);
+  if constexpr (FbShared<T, M, B, Q>::kHoles) {
+    load_twiddles<T, M, typename Fwd<M>::L, NT, 9, 8>(sh.tile, twm, tid);
+  } else {
+    load_twiddles<T, M, typename Fwd<M>::L, NT>(sh.tw, twm, tid);
+    if constexpr (!FbShared<T, M, B, Q>::kOneTw) load_twiddles<T, M, typename Inv<M>::L, NT>(sh.tw + M, twm, tid);
+  }
   fb_scalars(sh, it, A, tid);
   fb_dft_in<T, M, B, Q, NT>(sh, tid,
                                    [&](int jj, int z) { return it.base[(size_t)jj * (M / Q) + z]; });
