@@ -501,26 +501,11 @@ __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, TWF twf, TWI twi, i
   }
 }
 
-// build the stage-major table of schedule RL (N - 1 entries) in LDS from the plain table; entry
-// i goes to dst[STRIDE i + OFF] (STRIDE 9, OFF 8: the spare slots of a pad8 tile)
-template <typename T, int N, class RL, int NT, int STRIDE = 1, int OFF = 0>
+// copy COUNT entries of a stage-major table (built on the host, see TwS) into LDS; entry i goes
+// to dst[STRIDE i + OFF] (STRIDE 9, OFF 8: the spare slots of a pad8 tile)
+template <typename T, int COUNT, int NT, int STRIDE = 1, int OFF = 0>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src, int tid) {
-  for (int i = tid; i < N - 1; i += NT) {
-    int ns = 1, s = 0;
-#pragma unroll
-    for (int q = 1; q < RL::n; ++q)
-      if (i >= RL::ns(q) - 1) {
-        ns = RL::ns(q);
-        s = q;
-      }
-    int R = 1;
-#pragma unroll
-    for (int q = 0; q < RL::n; ++q)
-      if (q == s) R = RL::r[q];
-    const int rem = i - (ns - 1);
-    const int r = rem / ns + 1, k = rem - (r - 1) * ns;
-    dst[STRIDE * i + OFF] = src[k * r * (N / (ns * R))];
-  }
+  for (int i = tid; i < COUNT; i += NT) dst[STRIDE * i + OFF] = src[i];
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each XCD

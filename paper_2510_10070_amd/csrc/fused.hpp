@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   const bool sasha = g.method == 1;
   const double dz = g.lz / nz;
   cplx<T>* mytile = tile + sub * SLOTS;
-  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twy, tid);
+  load_twiddles<T, NY, NT>(tw, twy, tid);
 
   PlanePhase pp[POS];
 #pragma unroll
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   gmem<T>* phi = hbm(static_cast<T*>(br->phi));
   const int nx = g.nx;
   cplx<T>* mytile = tile + sub * SLOTS;
-  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twy, tid);
+  load_twiddles<T, NY, NT>(tw, twy, tid);
 
   cplx<T> acc[A][POS][2];
   PlanePhase pp[POS];
@@ -610,10 +610,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_pe
   const int tid = threadIdx.x;
   const FbItem<T> it = fb_item<T, M, B, Q>(br, t);
   if constexpr (FbShared<T, M, B, Q>::kHoles) {
-    load_twiddles<T, M, typename Fwd<M>::L, NT, 9, 8>(sh.tile, twm, tid);
+    load_twiddles<T, M - 1, NT, 9, 8>(sh.tile, twm, tid);
   } else {
-    load_twiddles<T, M, typename Fwd<M>::L, NT>(sh.tw, twm, tid);
-    if constexpr (!FbShared<T, M, B, Q>::kOneTw) load_twiddles<T, M, typename Inv<M>::L, NT>(sh.tw + M, twm, tid);
+    load_twiddles<T, FbShared<T, M, B, Q>::kOneTw ? M : 2 * M, NT>(sh.tw, twm, tid);
   }
   fb_scalars(sh, it, A, tid);
   fb_dft_in<T, M, B, Q, NT>(sh, tid,

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   gmem<cplx<T>>* W = hbm(static_cast<cplx<T>*>(br->W));
   gmem<double>* partials = (REMAP && g.method == 1) ? hbm(br->partials) : nullptr;  // SASHA sums only
 
-  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twg, tid);
+  load_twiddles<T, NY, NT>(tw, twg, tid);
   if (REMAP) {
     const double fy = br->fy;
     for (int my = tid; my < hy; my += NT) {
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   gmem<T>* phi = hbm(static_cast<T*>(br->phi));
   const int zn = min(ZC, nz - z0);
 
-  load_twiddles<T, NY, typename Fwd<NY>::L, NT>(tw, twg, tid);
+  load_twiddles<T, NY, NT>(tw, twg, tid);
   if (REMAP) {
     const double fy = br->fy;
     for (int my = tid; my < hy; my += NT) {
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
   const int zn = min(ZC, nz - z0);
   const size_t row = (size_t)hy * nz;
   gmem<cplx<T>>* base = hbm(static_cast<cplx<T>*>(br->W)) + (size_t)my * nz + z0;
-  load_twiddles<T, NX, typename Fwd<NX>::L, NT>(tw, twg, tid);
+  load_twiddles<T, NX, NT>(tw, twg, tid);
   fft_run<T, NX, typename Fwd<NX>::L, L, NT, D, false, false>(
       buf, TwS<T>{tw}, tid, [&](int e, int c) { return c < zn ? base[e * row + c] : mk<T>(T(0), T(0)); },
       [&](int e, int c, cplx<T> v) {
@@ -457,8 +457,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   gmem<const T>* zt = hbm(static_cast<const T*>(br->zt));
   const int pw0 = (t * WV + wave) * PPW;  // first pencil of this wavefront
 
-  load_twiddles<T, M, typename Fwd<M>::L, NT>(tw, twg, tid);
-  if constexpr (!kOneTw) load_twiddles<T, M, typename Inv<M>::L, NT>(tw + M, twg, tid);
+  load_twiddles<T, kOneTw ? M : 2 * M, NT>(tw, twg, tid);
   if (lane < PPW) {
     const int q = min(pw0 + lane, np - 1);
     const int mx = q / hy, my = q - mx * hy;

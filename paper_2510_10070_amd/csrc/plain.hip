@@ -212,7 +212,7 @@ static int ew_blocks(size_t n) {
   } while (0)
 
 hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* rec, const BoxRec* pad, GroupArgs one, int y_var, int x_var,
-                        const void* tw_x, const void* tw_y, const void* tw_m, hipStream_t st,
+                        const void* tws_x, const void* tws_y, const void* tw_m, hipStream_t st,
                         void (*mark)(void*, const char*), void* mark_ctx) {
   const BoxGeom& g = h_rec->g;
   const size_t nhalf = (size_t)g.nx * (g.ny / 2) * g.nz;
@@ -228,13 +228,13 @@ hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* rec, const BoxRec* pa
     PLAIN_STEP("plain_coef", hipLaunchKernelGGL(k_plain_coef, dim3(1), dim3(64), 0, st, rec));
   }
   PLAIN_STEP("plain_y_forward", {
-    hipError_t e = launch_y(0, true, false, g.ny, y_var, gy, yb, rec, tw_y, st);
+    hipError_t e = launch_y(0, true, false, g.ny, y_var, gy, yb, rec, tws_y, st);
     if (e) return e;
   });
   PLAIN_STEP("plain_remap", hipLaunchKernelGGL(k_plain_remap, dim3(ew_blocks(nhalf)), dim3(kEw), 0, st, rec, -1));
   PLAIN_STEP("plain_pad", hipLaunchKernelGGL(k_plain_pad, dim3(ew_blocks(npad)), dim3(kEw), 0, st, rec, pad));
   PLAIN_STEP("plain_x_forward", {
-    hipError_t e = launch_x(0, -1, g.nx, x_var, gx, xb, pad, tw_x, st);
+    hipError_t e = launch_x(0, -1, g.nx, x_var, gx, xb, pad, tws_x, st);
     if (e) return e;
   });
   PLAIN_STEP("plain_z_forward", {
@@ -247,13 +247,13 @@ hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* rec, const BoxRec* pa
     if (e) return e;
   });
   PLAIN_STEP("plain_x_inverse", {
-    hipError_t e = launch_x(0, +1, g.nx, x_var, gx, xb, pad, tw_x, st);
+    hipError_t e = launch_x(0, +1, g.nx, x_var, gx, xb, pad, tws_x, st);
     if (e) return e;
   });
   PLAIN_STEP("plain_extract", hipLaunchKernelGGL(k_plain_extract, dim3(ew_blocks(nhalf)), dim3(kEw), 0, st, rec, pad));
   PLAIN_STEP("plain_unremap", hipLaunchKernelGGL(k_plain_remap, dim3(ew_blocks(nhalf)), dim3(kEw), 0, st, rec, +1));
   PLAIN_STEP("plain_y_inverse", {
-    hipError_t e = launch_y(0, false, false, g.ny, y_var, gy, yb, rec, tw_y, st);
+    hipError_t e = launch_y(0, false, false, g.ny, y_var, gy, yb, rec, tws_y, st);
     if (e) return e;
   });
   if (g.method == 1)

@@ -110,7 +110,7 @@ hipError_t launch_gravity(int prec, const BoxGeom& g, double dy0, const void* ph
 // Plain (unfused) FP64 path for one box: rec0 views the half spectrum, rec_pad the padded one.
 constexpr int kPlainPartials = 1024;
 hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* d_rec0, const BoxRec* d_rec_pad, GroupArgs one,
-                        int y_var, int x_var, const void* tw_x, const void* tw_y, const void* tw_m,
+                        int y_var, int x_var, const void* tws_x, const void* tws_y, const void* tw_m,
                         hipStream_t st, void (*mark)(void*, const char*), void* mark_ctx);
 
 }  // namespace sbp

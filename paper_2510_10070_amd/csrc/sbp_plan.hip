@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/sbp.h"
+#include "fft_device.hpp"
 #include "sbp_internal.hpp"
 #include "tune.hpp"
 
@@ -146,9 +147,52 @@ void twiddles(int n, std::vector<long double>& re, std::vector<long double>& im)
   }
 }
 
+// stage-major table of schedule RL (the layout the transform kernels read, see TwS): stage s
+// (ns = product of the earlier radices, radix R) holds exp(-2 pi i k r/(ns R)) at
+// ns - 1 + (r - 1) ns + k; n slots, the last one unused
+template <class RL>
+void stage_major(int n, const std::vector<long double>& re, const std::vector<long double>& im,
+                 std::vector<long double>& ore, std::vector<long double>& oim) {
+  ore.assign(n, 0.0L);
+  oim.assign(n, 0.0L);
+  int ns = 1;
+  for (int s = 0; s < RL::n; ++s) {
+    const int R = RL::r[s];
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < ns; ++k) {
+        const int m = k * r * (n / (ns * R));
+        ore[ns - 1 + (r - 1) * ns + k] = re[m];
+        oim[ns - 1 + (r - 1) * ns + k] = im[m];
+      }
+    ns *= R;
+  }
+}
+
+// the forward schedule's table of length n, then the inverse schedule's
+bool stage_major_pair(int n, const std::vector<long double>& re, const std::vector<long double>& im,
+                      std::vector<long double>& ore, std::vector<long double>& oim) {
+  std::vector<long double> fr, fi, ir, ii;
+  bool ok = false;
+#define SBP_CASE(N_)                                                 \
+  if (n == N_) {                                                     \
+    stage_major<typename sbp::Fwd<N_>::L>(n, re, im, fr, fi);        \
+    stage_major<typename sbp::Inv<N_>::L>(n, re, im, ir, ii);        \
+    ok = true;                                                       \
+  }
+  SBP_FOR_EACH_LEN(SBP_CASE)
+#undef SBP_CASE
+  if (!ok) return false;
+  ore = fr;
+  oim = fi;
+  ore.insert(ore.end(), ir.begin(), ir.end());
+  oim.insert(oim.end(), ii.begin(), ii.end());
+  return true;
+}
+
 struct TableBuilder {
   std::vector<char> host;
   std::map<std::pair<int, int>, size_t> tw;  // (n, prec) -> offset
+  std::map<std::pair<int, int>, size_t> tws;  // (n, prec) -> offset of the stage-major pair
   size_t put(const void* p, size_t bytes) {
     size_t off = align_up(host.size());
     host.resize(off + bytes);
@@ -172,6 +216,26 @@ struct TableBuilder {
       off = put(v.data(), v.size() * sizeof(double));
     }
     tw[key] = off;
+    return off;
+  }
+  template <typename T> size_t put_cplx(const std::vector<long double>& re, const std::vector<long double>& im) {
+    std::vector<T> v(2 * re.size());
+    for (size_t m = 0; m < re.size(); ++m) {
+      v[2 * m] = (T)re[m];
+      v[2 * m + 1] = (T)im[m];
+    }
+    return put(v.data(), v.size() * sizeof(T));
+  }
+  // stage-major twiddles of length n: 2n entries, forward schedule then inverse schedule
+  size_t stage_twiddles(int n, int prec) {
+    auto key = std::make_pair(n, prec);
+    auto it = tws.find(key);
+    if (it != tws.end()) return it->second;
+    std::vector<long double> re, im, sre, sim;
+    twiddles(n, re, im);
+    stage_major_pair(n, re, im, sre, sim);  // n is a validated length
+    const size_t off = prec ? put_cplx<float>(sre, sim) : put_cplx<double>(sre, sim);
+    tws[key] = off;
     return off;
   }
 };
@@ -299,12 +363,12 @@ void build_launches(sbp_plan p) {
       const BoxInfo& b0 = p->boxes[kv.second[0]];
       switch (kind) {
         case sbp::kYFwd:
-        case sbp::kYInv: l.tw = b0.tw_y; break;
-        case sbp::kZ: l.tw = b0.tw_m; l.tw64 = b0.tw_m64; break;
+        case sbp::kYInv: l.tw = b0.tws_y; break;
+        case sbp::kZ: l.tw = b0.tws_m; l.tw64 = b0.tw_m64; break;
         case sbp::kFA:
-        case sbp::kFC: l.tw = b0.tw_y; l.tw64 = b0.tw_x; break;
-        case sbp::kFB: l.tw = b0.tw_m; l.tw64 = b0.tw_m64; break;
-        default: l.tw = b0.tw_x;
+        case sbp::kFC: l.tw = b0.tws_y; l.tw64 = b0.tw_x; break;
+        case sbp::kFB: l.tw = b0.tws_m; l.tw64 = b0.tw_m64; break;
+        default: l.tw = b0.tws_x;
       }
       p->launches.push_back(l);
     }
@@ -341,7 +405,7 @@ sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot) {
     const BoxInfo& bi = p->boxes[0];
     sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1};
     HIP_TRY(sbp::launch_plain(&p->master[0], p->d_recs, p->d_recs + 1, one, bi.var[sbp::kYFwd], bi.var[sbp::kXFwd],
-                              T + bi.tw_x, T + bi.tw_y, T + bi.tw_m, st, mk ? mark_cb : nullptr, mk));
+                              T + bi.tws_x, T + bi.tws_y, T + bi.tw_m, st, mk ? mark_cb : nullptr, mk));
     return SBP_OK;
   }
   for (const Launch& l : p->launches) {
@@ -599,9 +663,11 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       bi.pad = pad;
       bi.g = sbp::BoxGeom{b.nx, b.ny, b.nz, pad * b.nz, b.method, b.remap, b.lx, b.ly, b.lz, alpha * b.lz};
       bi.tw_x = tb.twiddle(b.nx, prec);
-      bi.tw_y = tb.twiddle(b.ny, prec);
       bi.tw_m = tb.twiddle(pad * b.nz, prec);
       bi.tw_m64 = tb.twiddle(pad * b.nz, 0);
+      bi.tws_x = tb.stage_twiddles(b.nx, prec);
+      bi.tws_y = tb.stage_twiddles(b.ny, prec);
+      bi.tws_m = tb.stage_twiddles(pad * b.nz, prec);
       std::vector<long double> s2, ks, kz2;
       ztables(bi.g, pad, s2, ks, kz2);
       bi.zt64[0] = put_vec<double>(tb, s2);

@@ -29,7 +29,8 @@ struct Launch {
 struct BoxInfo {
   BoxGeom g;
   int pad = 2;
-  size_t tw_x = 0, tw_y = 0, tw_m = 0, tw_m64 = 0;  // offsets into the table block
+  size_t tw_x = 0, tw_m = 0, tw_m64 = 0;  // offsets into the table block: plain twiddles
+  size_t tws_x = 0, tws_y = 0, tws_m = 0;           // stage-major twiddles, forward then inverse
   size_t zt = 0, zt64[3] = {0, 0, 0}, k0h = 0;
   size_t ws_off = 0;   // half spectrum (plain: padded spectrum)
   size_t ws2_off = 0;  // plain: unpadded half spectrum
