@@ -16,8 +16,11 @@ namespace sbp {
 
 constexpr int kFusedAC = 512;  // threads of passes A and C
 
-// real z cells per pass-A/C tile: variant 1 = 64-byte rows, variant 0 = 32-byte rows
-template <typename T, int V> constexpr int fa_zc() { return (V ? 64 : 32) / (int)sizeof(T); }
+// real z cells per pass-A/C tile: variant 0 = 32-byte rows, 1 = 64-byte rows, 2 = 16-byte rows
+template <typename T, int V> constexpr int fa_zc() { return (V == 1 ? 64 : V == 2 ? 16 : 32) / (int)sizeof(T); }
+// threads per pass-A/C block: variant 2 tiles are half as wide and take half the threads, so
+// that two blocks fit on a CU at the register count of pass C
+template <int V> constexpr int fa_threads() { return V == 2 ? kFusedAC / 2 : kFusedAC; }
 
 // four-step split used by the fused schedule: B = 16 pencils per pass-B block, A = Nx/16
 constexpr int kFusedB16 = 16;
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
-  constexpr int NT = kFusedAC;
+  constexpr int NT = fa_threads<V>();
   constexpr int PG = A < 4 ? A : 4;  // planes transformed side by side
   constexpr int TNT = NT / PG;       // threads per plane transform
   constexpr int HY = NY / 2;
@@ -167,7 +170,6 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   }
 
   // A-point DFT across planes, twiddle w_Nx^(j k1), store
-  const int nx = g.nx;
 #pragma unroll
   for (int i = 0; i < POS; ++i) {
     const int q = tid + i * NT;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
     Dft<A, -1, T>::run(vb);
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
-      const cplx<T> w = twx[(j * k1) % nx];
+      const cplx<T> w = twx[j * k1];  // j k1 < B A = Nx
       const cplx<T> ra = cmul<T>(va[k1], w), rb = cmul<T>(vb[k1], w);
       gmem<cplx<T>>* dst = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
       if constexpr (sizeof(T) == 4) {
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
-  constexpr int NT = kFusedAC;
+  constexpr int NT = fa_threads<V>();
   constexpr int PG = A < 4 ? A : 4;
   constexpr int TNT = NT / PG;
   constexpr int HY = NY / 2;
@@ -230,7 +232,6 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   const int zn = min(ZC, nz - z0);
   gmem<const cplx<T>>* W = hbm(static_cast<const cplx<T>*>(br->W));
   gmem<T>* phi = hbm(static_cast<T*>(br->phi));
-  const int nx = g.nx;
   cplx<T>* mytile = tile + sub * SLOTS;
   load_twiddles<T, NY, NT>(tw, twy, tid);
 
@@ -242,24 +243,28 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
     const int ky = q < QN ? q / NB : 0, c = q < QN ? q - ky * NB : 0;
     pp[i].init(ky, j, B, br->fy);
     cplx<T> va[A], vb[A];
+    // one branch around all A loads, so that they issue back to back
+    if (q < QN && 2 * c < zn) {
+      gmem<const cplx<T>>* src = W + ((size_t)ky * B + j) * nz + z0 + 2 * c;
+      const size_t plane = (size_t)HY * B * nz;  // W stride between consecutive k1
 #pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) {
-      va[k1] = vb[k1] = mk<T>(T(0), T(0));
-      if (q < QN && 2 * c < zn) {
-        gmem<const cplx<T>>* src = W + (((size_t)k1 * HY + ky) * B + j) * nz + z0 + 2 * c;
+      for (int k1 = 0; k1 < A; ++k1) {
         cplx<T> a0, b0;
         if constexpr (sizeof(T) == 4) {
-          const float4 v4 = *reinterpret_cast<gmem<const float4>*>(src);
+          const float4 v4 = *reinterpret_cast<gmem<const float4>*>(src + k1 * plane);
           a0 = mk<T>(v4.x, v4.y);
           b0 = mk<T>(v4.z, v4.w);
         } else {
-          a0 = src[0];
-          b0 = src[1];
+          a0 = src[k1 * plane];
+          b0 = src[k1 * plane + 1];
         }
-        const cplx<T> w = twx[(j * k1) % nx];
+        const cplx<T> w = twx[j * k1];  // j k1 < B A = Nx
         va[k1] = cmulc<T>(a0, w);
         vb[k1] = cmulc<T>(b0, w);
       }
+    } else {
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) va[k1] = vb[k1] = mk<T>(T(0), T(0));
     }
     Dft<A, +1, T>::run(va);
     Dft<A, +1, T>::run(vb);
@@ -632,7 +637,7 @@ template <> hipError_t launch_fused_impl<double>(int, int, int, int, int, bool, 
                                                  const void*, hipStream_t);
 
 template <typename T> int fused_ac_tiles_t(const BoxGeom& g, int variant) {
-  const int zc = variant ? fa_zc<T, 1>() : fa_zc<T, 0>();
+  const int zc = variant == 1 ? fa_zc<T, 1>() : variant == 2 ? fa_zc<T, 2>() : fa_zc<T, 0>();
   return kFusedB16 * ((g.nz + zc - 1) / zc);
 }
 

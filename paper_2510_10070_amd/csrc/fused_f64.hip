@@ -3,6 +3,24 @@
 
 namespace sbp {
 
+// variant 2 (16-byte rows, half-size blocks): pass C only, for Ny <= 256 (one position per
+// thread); anything else is rejected, never replaced, since the plan sized the grid for it
+template <typename T, int NY, int A, int B>
+static hipError_t launch_fc_narrow(int kind, bool lin, int blocks, GroupArgs ga, const BoxRec* recs,
+                                   const cplx<T>* t1, const cplx<T>* t2, hipStream_t st) {
+  if constexpr (NY <= 256) {
+    if (kind != 2) return hipErrorInvalidValue;
+    if (lin)
+      hipLaunchKernelGGL((k_fc<T, NY, A, B, 2, true>), dim3(blocks), dim3(fa_threads<2>()), 0, st, ga, recs, t1, t2);
+    else
+      hipLaunchKernelGGL((k_fc<T, NY, A, B, 2, false>), dim3(blocks), dim3(fa_threads<2>()), 0, st, ga, recs, t1, t2);
+    return hipGetLastError();
+  } else {
+    (void)kind; (void)lin; (void)blocks; (void)ga; (void)recs; (void)t1; (void)t2; (void)st;
+    return hipErrorInvalidValue;
+  }
+}
+
 // kind: 0 = pass A (len = Ny), 1 = pass B (len = M, q = padding), 2 = pass C (len = Ny);
 // a = A = Nx/16.  tw: y twiddles (A, C) or z twiddles (B); tw2: x twiddles (A, C) or the
 // double z twiddles (B).
@@ -13,7 +31,6 @@ hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int 
   constexpr int B = kFusedB16;
   const dim3 grid(blocks);
   const cplx<T>* t1 = static_cast<const cplx<T>*>(tw);
-  (void)variant;
   if (kind == 1) {
     (void)tw2;
 #define SBP_CASE(M_)                \
@@ -27,16 +44,17 @@ hipError_t launch_fused_impl<double>(int kind, int len, int a, int variant, int 
     return hipErrorInvalidValue;
   }
   const cplx<T>* t2 = static_cast<const cplx<T>*>(tw2);
-#define SBP_AC(NY_, A_)                                                                                          \
-  if (len == NY_ && a == A_) {                                                                                    \
-    if (kind == 0) {                                                                                              \
-      if (lin) hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, true>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2); \
-      else hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, false>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);   \
-    } else {                                                                                                      \
-      if (lin) hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0, true>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2); \
-      else hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0, false>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);   \
-    }                                                                                                             \
-    return hipGetLastError();                                                                                     \
+#define SBP_AC(NY_, A_)                                                      \
+  if (len == NY_ && a == A_) {                                              \
+    if (variant == 2) return launch_fc_narrow<T, NY_, A_, B>(kind, lin, blocks, ga, recs, t1, t2, st); \
+    if (kind == 0) {                                                        \
+      if (lin) hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2); \
+      else hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);   \
+    } else {                                                                \
+      if (lin) hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2); \
+      else hipLaunchKernelGGL((k_fc<T, NY_, A_, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);   \
+    }                                                                       \
+    return hipGetLastError();                                               \
   }
 #define SBP_NY(NY_) SBP_AC(NY_, 1) SBP_AC(NY_, 2) SBP_AC(NY_, 4) SBP_AC(NY_, 8) SBP_AC(NY_, 16)
   SBP_NY(16) SBP_NY(32) SBP_NY(64) SBP_NY(128) SBP_NY(256) SBP_NY(512)

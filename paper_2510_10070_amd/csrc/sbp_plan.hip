@@ -722,6 +722,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
           most = std::max(most, sbp::y_tiles(prec, bi.g, v));
           most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, v));
         }
+        most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, 2));
         bi.npartials = most;
       }
       bi.part_off = npart;

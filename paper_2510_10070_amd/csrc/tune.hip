@@ -17,10 +17,10 @@
 namespace sbp {
 
 void default_variants(int prec, const BoxGeom& g, int var[kKinds]) {
-  (void)prec;
-  (void)g;
   for (int k = 0; k < 5; ++k) var[k] = 1;
-  for (int k = 5; k < kKinds; ++k) var[k] = 0;  // the fused kernels have one tile shape
+  for (int k = 5; k < kKinds; ++k) var[k] = 0;
+  // float pass C in half-size blocks with 16-byte rows: two blocks per CU at its register count
+  if (prec && g.ny <= 256) var[kFC] = 2;
 }
 
 namespace {
