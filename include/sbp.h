@@ -77,8 +77,8 @@ typedef enum { SBP_REMAP_SPECTRAL = 0, SBP_REMAP_LINEAR = 1 } sbp_remap;
                                    three HBM round trips of the half spectrum.  It applies to
                                    power-of-two 16 <= nx <= 256, 16 <= ny <= 512 and
                                    32 <= pad*nz <= 512; other boxes of the plan run five-pass.
-                                   Without either schedule flag a plan picks per precision: fused
-                                   for SBP_FP32, five-pass for SBP_FP64 (the faster on gfx950).
+                                   Without either schedule flag a plan takes the fused schedule
+                                   wherever it applies (the faster on gfx950 in both precisions).
                                    Both flags together are SBP_E_ARG. */
 
 /* Geometry, method and remap of one box.

@@ -21,6 +21,8 @@ template <typename T, int V> constexpr int fa_zc() { return (V == 1 ? 64 : V == 
 // threads per pass-A/C block: variant 2 tiles are half as wide and take half the threads, so
 // that two blocks fit on a CU at the register count of pass C
 template <int V> constexpr int fa_threads() { return V == 2 ? kFusedAC / 2 : kFusedAC; }
+// variant 3 (split passes A and C, k_fas / k_fcs): four z cells per tile in either precision
+constexpr int kSplitZC = 4;
 
 // four-step split used by the fused schedule: B = 16 pencils per pass-B block, A = Nx/16
 constexpr int kFusedB16 = 16;
@@ -344,6 +346,238 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
 }
 
 // ------------------------------------------------------------------------------------------
+// Split passes A and C (tile variant 3: four z cells per tile, Ny <= 256).  The two real z
+// columns of a position (ky, c), which share one complex y transform, are held by a lane pair,
+// one column per lane, so that each thread keeps one complex value per plane instead of two:
+// half the registers, all 512 threads busy (with four z cells and Ny = 256 a tile has 256
+// positions), eight planes transformed side by side.
+
+template <typename T, int NY, int A, int B, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+  constexpr int ZC = kSplitZC;
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kFusedAC;
+  constexpr int HY = NY / 2;
+  constexpr int QN = HY * NB;  // positions (ky, c)
+  static_assert(2 * QN <= NT, "one position per lane pair");
+  constexpr int PG = A < 8 ? A : 8;
+  constexpr int TNT = NT / PG;
+  constexpr int SLOTS = lds_slots(NY * NB);
+  using L = Tile<NB, NB, 1, true>;
+  __shared__ cplx<T> tile[PG * SLOTS];
+  __shared__ cplx<T> tw[NY];
+  __shared__ double red[2][NT / 64];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int sub = tid / TNT, stid = tid - sub * TNT;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int j = t / nzc;
+  const int z0 = (t - j * nzc) * ZC;
+  const int zn = min(ZC, nz - z0);
+  gmem<const T>* rho = hbm(static_cast<const T*>(br->rho));
+  gmem<cplx<T>>* W = hbm(static_cast<cplx<T>*>(br->W));
+  const bool sasha = g.method == 1;
+  const double dz = g.lz / nz;
+  cplx<T>* mytile = tile + sub * SLOTS;
+  load_twiddles<T, NY, NT>(tw, twy, tid);
+
+  const int q = tid >> 1, h = tid & 1;  // position and column of this lane
+  const bool qv = q < QN;
+  const int ky = qv ? q / NB : 0, c = qv ? q - ky * NB : 0;
+  PlanePhase pp;
+  pp.init(ky, j, B, br->fy);
+  cplx<T> acc[A];
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int a0 = 0; a0 < A; a0 += PG) {
+    // PG thread groups transform planes a0 .. a0+PG-1 (x = j + B a) into their LDS tiles
+    const int x = j + B * (a0 + sub);
+    gmem<const T>* src = rho + (size_t)x * NY * nz + z0;
+    YInterp yi;
+    if (LIN) yi.init(-br->shy * (x + 0.5), NY);
+    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true>(
+        mytile, TwS<T>{tw}, stid,
+        [&](int e, int cc) {
+          cplx<T> v = mk<T>(T(0), T(0));
+          if (2 * cc < zn) {
+            auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * cc); };
+            v = LIN ? yi.sample<T>(e, NY, ld) : ld(e);
+            if (sasha) {
+              const double za = -0.5 * g.lz + (z0 + 2 * cc + 0.5) * dz;
+              s0 += (double)v.x + (double)v.y;
+              s1 += za * (double)v.x + (za + dz) * (double)v.y;
+            }
+          }
+          return v;
+        },
+        [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; });
+    __syncthreads();
+    // each lane separates its column of its position from the Hermitian pair and remaps it
+#pragma unroll
+    for (int sp = 0; sp < PG; ++sp) {
+      const cplx<T>* tl = tile + sp * SLOTS;
+      acc[a0 + sp] = mk<T>(T(0), T(0));
+      if (qv) {
+        const cplx<T> c1 = tl[L::at(ky, c)];
+        const cplx<T> c2 = tl[L::at((NY - ky) % NY, c)];
+        const cplx<T> v = h == 0 ? mk<T>(T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y))
+                                 : mk<T>(T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x));
+        acc[a0 + sp] = cmul<T>(v, mk<T>((T)pp.pr, (T)pp.pi));
+      }
+      pp.step();
+    }
+    __syncthreads();  // the tiles are reused by the next planes
+  }
+
+  if (sasha) {
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_down(s0, o);
+      s1 += __shfl_down(s1, o);
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = s0;
+      red[1][tid >> 6] = s1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sa = 0.0, sb = 0.0;
+      for (int i = 0; i < NT / 64; ++i) {
+        sa += red[0][i];
+        sb += red[1][i];
+      }
+      hbm(br->partials)[2 * t] = sa;
+      hbm(br->partials)[2 * t + 1] = sb;
+    }
+  }
+
+  // A-point DFT across planes, twiddle w_Nx^(j k1), store this lane's column
+  Dft<A, -1, T>::run(acc);
+  if (qv && 2 * c + h < zn) {
+    gmem<cplx<T>>* dst = W + ((size_t)ky * B + j) * nz + z0 + 2 * c + h;
+    const size_t plane = (size_t)HY * B * nz;  // W stride between consecutive k1
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) dst[k1 * plane] = cmul<T>(acc[k1], twx[j * k1]);  // j k1 < Nx
+  }
+}
+
+// Inverse of k_fas.  After the inverse A-point DFT and the remap phase the lane pair swaps its
+// values, and each lane writes one of the two Hermitian slots of the position.
+template <typename T, int NY, int A, int B, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fcs(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+  constexpr int ZC = kSplitZC;
+  constexpr int NB = ZC / 2;
+  constexpr int NT = kFusedAC;
+  constexpr int HY = NY / 2;
+  constexpr int QN = HY * NB;  // positions (ky, c)
+  static_assert(2 * QN <= NT, "one position per lane pair");
+  constexpr int PG = A < 8 ? A : 8;
+  constexpr int TNT = NT / PG;
+  constexpr int SLOTS = lds_slots(NY * NB);
+  using L = Tile<NB, NB, 1, true>;
+  __shared__ cplx<T> tile[PG * SLOTS];
+  __shared__ cplx<T> tw[NY];
+
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const BoxGeom g = br->g;
+  const int tid = threadIdx.x;
+  const int sub = tid / TNT, stid = tid - sub * TNT;
+  const int nz = g.nz;
+  const int nzc = (nz + ZC - 1) / ZC;
+  const int j = t / nzc;
+  const int z0 = (t - j * nzc) * ZC;
+  const int zn = min(ZC, nz - z0);
+  gmem<const cplx<T>>* W = hbm(static_cast<const cplx<T>*>(br->W));
+  gmem<T>* phi = hbm(static_cast<T*>(br->phi));
+  cplx<T>* mytile = tile + sub * SLOTS;
+  load_twiddles<T, NY, NT>(tw, twy, tid);
+
+  const int q = tid >> 1, h = tid & 1;  // position and column of this lane
+  const bool qv = q < QN;
+  const int ky = qv ? q / NB : 0, c = qv ? q - ky * NB : 0;
+  PlanePhase pp;
+  pp.init(ky, j, B, br->fy);
+  cplx<T> acc[A];
+  if (qv && 2 * c + h < zn) {
+    gmem<const cplx<T>>* src = W + ((size_t)ky * B + j) * nz + z0 + 2 * c + h;
+    const size_t plane = (size_t)HY * B * nz;  // W stride between consecutive k1
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) acc[k1] = cmulc<T>(src[k1 * plane], twx[j * k1]);  // j k1 < Nx
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) acc[k1] = mk<T>(T(0), T(0));
+  }
+  Dft<A, +1, T>::run(acc);
+
+  const bool sasha = g.method == 1;
+  double c2 = 0.0, c1 = 0.0;
+  if (sasha) {
+    c2 = hbm(br->coef)->c2;
+    c1 = hbm(br->coef)->c1;
+  }
+  const double dz = g.lz / nz;
+#pragma unroll
+  for (int a0 = 0; a0 < A; a0 += PG) {
+    // the lane pairs write their positions of planes a0 .. a0+PG-1 as Hermitian columns
+#pragma unroll
+    for (int sp = 0; sp < PG; ++sp) {
+      cplx<T>* tl = tile + sp * SLOTS;
+      if (tid < NB) tl[L::at(HY, tid)] = mk<T>(T(0), T(0));  // y Nyquist
+      const cplx<T> mine = cmulc<T>(acc[a0 + sp], mk<T>((T)pp.pr, (T)pp.pi));  // exp(-i theta), conjugated
+      const cplx<T> other = mk<T>(__shfl_xor(mine.x, 1), __shfl_xor(mine.y, 1));
+      const cplx<T> av = h ? other : mine, bv = h ? mine : other;
+      if (qv) {
+        if (ky == 0) {
+          if (h == 0) tl[L::at(0, c)] = mk<T>(av.x, bv.x);
+        } else if (h == 0) {
+          tl[L::at(ky, c)] = mk<T>(av.x - bv.y, av.y + bv.x);
+        } else {
+          tl[L::at(NY - ky, c)] = mk<T>(av.x + bv.y, bv.x - av.y);
+        }
+      }
+      pp.step();
+    }
+    __syncthreads();
+    // PG thread groups run the inverse y transforms of their planes straight to phi
+    const int x = j + B * (a0 + sub);
+    gmem<T>* dst = phi + (size_t)x * NY * nz + z0;
+    auto store = [&](int e, int cc, cplx<T> v) {
+      if (2 * cc < zn) {
+        if (sasha) {
+          const double za = -0.5 * g.lz + (z0 + 2 * cc + 0.5) * dz;
+          const double zb = za + dz;
+          v.x = (T)((double)v.x + (c2 * za + c1) * za);
+          v.y = (T)((double)v.y + (c2 * zb + c1) * zb);
+        }
+        *reinterpret_cast<gmem<cplx<T>>*>(dst + (size_t)e * nz + 2 * cc) = v;
+      }
+    };
+    if constexpr (LIN) {
+      YInterp yi;
+      yi.init(br->shy * (x + 0.5), NY);
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true>(
+          mytile, TwS<T>{tw}, stid, [&](int e, int cc) { return mytile[L::at(e, cc)]; },
+          [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; });
+      __syncthreads();
+      for (int w = stid; w < NY * NB; w += TNT) {
+        const int cc = w % NB, e = w / NB;
+        store(e, cc, yi.sample<T>(e, NY, [&](int y) { return mytile[L::at(y, cc)]; }));
+      }
+    } else {
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
+          mytile, TwS<T>{tw}, stid, [&](int e, int cc) { return mytile[L::at(e, cc)]; }, store);
+    }
+    __syncthreads();  // the tiles are rebuilt for the next planes
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Pass B: one block per (k1, my) item.
 // The B-point DFT across the j pencils runs in registers (one thread per z) and parks the B
 // pencils in the LDS tile.  Every wavefront then takes tuples of Q pencil groups (PW pencils
@@ -637,7 +871,7 @@ template <> hipError_t launch_fused_impl<double>(int, int, int, int, int, bool, 
                                                  const void*, hipStream_t);
 
 template <typename T> int fused_ac_tiles_t(const BoxGeom& g, int variant) {
-  const int zc = variant == 1 ? fa_zc<T, 1>() : variant == 2 ? fa_zc<T, 2>() : fa_zc<T, 0>();
+  const int zc = variant == 1 ? fa_zc<T, 1>() : variant == 2 ? fa_zc<T, 2>() : variant == 3 ? kSplitZC : fa_zc<T, 0>();
   return kFusedB16 * ((g.nz + zc - 1) / zc);
 }
 

@@ -3,20 +3,29 @@
 
 namespace sbp {
 
-// variant 2 (16-byte rows, half-size blocks): pass C only, for Ny <= 256 (one position per
-// thread); anything else is rejected, never replaced, since the plan sized the grid for it
+// variants for Ny <= 256 only: 2 (pass C in 256-thread blocks over 16-byte rows) and 3 (split
+// passes A and C, k_fas / k_fcs); anything else is rejected, never replaced, since the plan
+// sized the grid for the variant
 template <typename T, int NY, int A, int B>
-static hipError_t launch_fc_narrow(int kind, bool lin, int blocks, GroupArgs ga, const BoxRec* recs,
+static hipError_t launch_ac_narrow(int kind, int variant, bool lin, int blocks, GroupArgs ga, const BoxRec* recs,
                                    const cplx<T>* t1, const cplx<T>* t2, hipStream_t st) {
   if constexpr (NY <= 256) {
-    if (kind != 2) return hipErrorInvalidValue;
-    if (lin)
-      hipLaunchKernelGGL((k_fc<T, NY, A, B, 2, true>), dim3(blocks), dim3(fa_threads<2>()), 0, st, ga, recs, t1, t2);
-    else
-      hipLaunchKernelGGL((k_fc<T, NY, A, B, 2, false>), dim3(blocks), dim3(fa_threads<2>()), 0, st, ga, recs, t1, t2);
+    const dim3 grid(blocks);
+    if (variant == 2 && kind == 2) {
+      if (lin) hipLaunchKernelGGL((k_fc<T, NY, A, B, 2, true>), grid, dim3(fa_threads<2>()), 0, st, ga, recs, t1, t2);
+      else hipLaunchKernelGGL((k_fc<T, NY, A, B, 2, false>), grid, dim3(fa_threads<2>()), 0, st, ga, recs, t1, t2);
+    } else if (variant == 3 && kind == 0) {
+      if (lin) hipLaunchKernelGGL((k_fas<T, NY, A, B, true>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);
+      else hipLaunchKernelGGL((k_fas<T, NY, A, B, false>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);
+    } else if (variant == 3 && kind == 2) {
+      if (lin) hipLaunchKernelGGL((k_fcs<T, NY, A, B, true>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);
+      else hipLaunchKernelGGL((k_fcs<T, NY, A, B, false>), grid, dim3(kFusedAC), 0, st, ga, recs, t1, t2);
+    } else {
+      return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   } else {
-    (void)kind; (void)lin; (void)blocks; (void)ga; (void)recs; (void)t1; (void)t2; (void)st;
+    (void)kind; (void)variant; (void)lin; (void)blocks; (void)ga; (void)recs; (void)t1; (void)t2; (void)st;
     return hipErrorInvalidValue;
   }
 }
@@ -46,7 +55,7 @@ hipError_t launch_fused_impl<float>(int kind, int len, int a, int variant, int q
   const cplx<T>* t2 = static_cast<const cplx<T>*>(tw2);
 #define SBP_AC(NY_, A_)                                                      \
   if (len == NY_ && a == A_) {                                              \
-    if (variant == 2) return launch_fc_narrow<T, NY_, A_, B>(kind, lin, blocks, ga, recs, t1, t2, st); \
+    if (variant >= 2) return launch_ac_narrow<T, NY_, A_, B>(kind, variant, lin, blocks, ga, recs, t1, t2, st); \
     if (kind == 0) {                                                        \
       if (lin) hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2); \
       else hipLaunchKernelGGL((k_fa<T, NY_, A_, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);   \

@@ -702,7 +702,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
         bi.k0h = put_vec<double>(tb, h);
       }
       sbp::default_variants(prec, bi.g, bi.var);
-      const bool want_fused = (flags & SBP_FLAG_FUSED) || (!(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS)) && prec == 1);
+      const bool want_fused = (flags & SBP_FLAG_FUSED) || !(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS));
       bi.fused = want_fused && sbp::fused_ok(bi.g);
       const size_t n = (size_t)b.nx * b.ny * b.nz;
       bi.data_bytes = n * w;
@@ -723,6 +723,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
           most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, v));
         }
         most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, 2));
+        most = std::max(most, sbp::fused_ac_tiles(prec, bi.g, 3));
         bi.npartials = most;
       }
       bi.part_off = npart;
