@@ -123,6 +123,26 @@ template <int D, typename T> struct Dft<8, D, T> {
   }
 };
 
+// 6 = 3 x 2: DFT3 over the even and the odd inputs, then radix-2 with the twiddles w6^k
+template <int D, typename T> struct Dft<6, D, T> {
+  static __device__ __forceinline__ void run(cplx<T>* v) {
+    const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+    cplx<T> e[3] = {v[0], v[2], v[4]};
+    cplx<T> o[3] = {v[1], v[3], v[5]};
+    Dft<3, D, T>::run(e);
+    Dft<3, D, T>::run(o);
+    // w6^1 = 1/2 + i D sqrt(3)/2, w6^2 = -1/2 + i D sqrt(3)/2
+    const cplx<T> o1 = mk<T>(T(0.5) * o[1].x - D * h * o[1].y, T(0.5) * o[1].y + D * h * o[1].x);
+    const cplx<T> o2 = mk<T>(-T(0.5) * o[2].x - D * h * o[2].y, -T(0.5) * o[2].y + D * h * o[2].x);
+    v[0] = cadd<T>(e[0], o[0]);
+    v[3] = csub<T>(e[0], o[0]);
+    v[1] = cadd<T>(e[1], o1);
+    v[4] = csub<T>(e[1], o1);
+    v[2] = cadd<T>(e[2], o2);
+    v[5] = csub<T>(e[2], o2);
+  }
+};
+
 template <int D, typename T> struct Dft<1, D, T> {
   static __device__ __forceinline__ void run(cplx<T>*) {}
 };

@@ -26,10 +26,19 @@ constexpr int kSplitZC = 4;
 
 // four-step split used by the fused schedule: B = 16 pencils per pass-B block, A = Nx/16
 constexpr int kFusedB16 = 16;
+// instantiated lengths: Nx = 16 A with A in {1, 2, 4, 6, 8, 16}; Ny a power of two in
+// [16, 512] or 96; M = pad Nz a power of two in [32, 512] or 192
 inline bool fused_supported(int nx, int ny, int m) {
   auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
-  return pow2(nx) && nx >= 16 && nx <= 256 && pow2(ny) && ny >= 16 && ny <= 512 && pow2(m) && m >= 32 &&
-         m <= 512;
+  return ((pow2(nx) && nx >= 16 && nx <= 256) || nx == 96) && ((pow2(ny) && ny >= 16 && ny <= 512) || ny == 96) &&
+         ((pow2(m) && m >= 32 && m <= 512) || m == 192);
+}
+// planes transformed side by side in passes A and C: the largest power of two that divides A,
+// capped (the plane groups must tile the A planes and the threads)
+template <int A, int CAP> constexpr int fa_pg() {
+  int p = 1;
+  while (2 * p <= CAP && A % (2 * p) == 0) p *= 2;
+  return p;
 }
 
 // remap phase of plane x = j + B a as P_j Q^a in double: exp(-i 2 pi my (2x+1) fy)
@@ -65,7 +74,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = fa_threads<V>();
-  constexpr int PG = A < 4 ? A : 4;  // planes transformed side by side
+  constexpr int PG = fa_pg<A, 4>();  // planes transformed side by side
   constexpr int TNT = NT / PG;       // threads per plane transform
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;        // output positions (ky, c) of one plane
@@ -212,7 +221,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = fa_threads<V>();
-  constexpr int PG = A < 4 ? A : 4;
+  constexpr int PG = fa_pg<A, 4>();
   constexpr int TNT = NT / PG;
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;
@@ -361,7 +370,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;  // positions (ky, c)
   static_assert(2 * QN <= NT, "one position per lane pair");
-  constexpr int PG = A < 8 ? A : 8;
+  constexpr int PG = fa_pg<A, 8>();
   constexpr int TNT = NT / PG;
   constexpr int SLOTS = lds_slots(NY * NB);
   using L = Tile<NB, NB, 1, true>;
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fcs(GroupArgs ga, const BoxRec* __
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;  // positions (ky, c)
   static_assert(2 * QN <= NT, "one position per lane pair");
-  constexpr int PG = A < 8 ? A : 8;
+  constexpr int PG = fa_pg<A, 8>();
   constexpr int TNT = NT / PG;
   constexpr int SLOTS = lds_slots(NY * NB);
   using L = Tile<NB, NB, 1, true>;
@@ -840,7 +849,7 @@ __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbIte
 
 template <typename T, int M, int B, int Q>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_per_eu<T, M, B, Q>()))) void k_fb(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                            const cplx<T>* __restrict__ twm, int A) {
+                                            const cplx<T>* __restrict__ twm) {
   constexpr int WV = fb_waves<M, B, Q>();
   constexpr int NT = 64 * WV;
   __shared__ FbShared<T, M, B, Q> sh;
@@ -853,7 +862,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_pe
   } else {
     load_twiddles<T, FbShared<T, M, B, Q>::kOneTw ? M : 2 * M, NT>(sh.tw, twm, tid);
   }
-  fb_scalars(sh, it, A, tid);
+  fb_scalars(sh, it, it.br->g.nx / B, tid);  // A = Nx/B of this block's box
   fb_dft_in<T, M, B, Q, NT>(sh, tid,
                                    [&](int jj, int z) { return it.base[(size_t)jj * (M / Q) + z]; });
   __syncthreads();

@@ -1,0 +1,7 @@
+// Fused passes A and C for float, Ny in {512}.
+#include "fused_launch.hpp"
+
+namespace sbp {
+template hipError_t launch_ac_ny<float, 512>(int, int, int, bool, GroupArgs, int, const BoxRec*, const cplx<float>*,
+                                              const cplx<float>*, hipStream_t);
+}  // namespace sbp

@@ -1,0 +1,7 @@
+// Fused passes A and C for double, Ny in {256}.
+#include "fused_launch.hpp"
+
+namespace sbp {
+template hipError_t launch_ac_ny<double, 256>(int, int, int, bool, GroupArgs, int, const BoxRec*, const cplx<double>*,
+                                              const cplx<double>*, hipStream_t);
+}  // namespace sbp

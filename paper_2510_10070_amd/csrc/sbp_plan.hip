@@ -340,7 +340,8 @@ void build_launches(sbp_plan p) {
       const BoxInfo& bi = p->boxes[b];
       if (!kind_applies(bi, kind)) continue;
       const int q = (kind == sbp::kZ || kind == sbp::kFB) ? bi.pad : 0;
-      const int a = kind >= sbp::kFA ? sbp::fused_a(bi.g) : 0;
+      // pass B reads A = Nx/16 from each box's record, so its groups mix A
+      const int a = (kind == sbp::kFA || kind == sbp::kFC) ? sbp::fused_a(bi.g) : 0;
       const int lin = (kind == sbp::kFA || kind == sbp::kFC) && bi.g.remap == SBP_REMAP_LINEAR;
       groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a, lin)].push_back(b);
     }

@@ -191,6 +191,8 @@ FUSED_SHAPES = [
     (256, 16, 16, 1.0, 1.0, 1.0, 2, 0.0),
     (16, 512, 16, 1.0, 4.0, 1.0, 2, 0.0),
     (16, 16, 256, 1.0, 1.0, 2.0, 2, 0.0),
+    (96, 96, 96, 1.0, 1.5, 1.0, 2, 0.0),  # A = 6, Ny = 96, M = 192
+    (96, 16, 32, 1.0, 1.0, 1.0, 2, 0.0),
 ]
 
 
