@@ -1,10 +1,10 @@
 """Parity at the full sizes of the measured workloads, in the launch configurations the
 benchmark uses.
 
-* 256^3 random-field workload: the benchmark's FP32 plan (fused, autotuned, graph-replayed) and
-  its FP64 plan (graph-replayed), element by element against the full FP64 oracle.
-* 128^3 log-normal workload (FP32) and the 64-box batch (FP32, autotuned, graph-replayed, boxes
-  of uneven size and shear), against the oracle box by box.
+* 256^3 random-field workload: the benchmark's FP32 and FP64 plans (fused, autotuned), launched
+  directly and graph-replayed, element by element against the full FP64 oracle.
+* 128^3 log-normal workload (FP32) and the 64-box batch (FP32, autotuned, direct and
+  graph-replayed, boxes of uneven size and shear), against the oracle box by box.
 * 1024 x 1024 x 256 clumpy box (FP32).  The oracle does not finish there in test time, so:
     - a sheared plane wave at full size is checked at sampled points against the z profiles the
       oracle computes on a small horizontal grid of the same box (the operator is diagonal in the
@@ -33,14 +33,15 @@ def _box(b, method="vgf"):
     return dict(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, pad=2, alpha=0.0, method=method)
 
 
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_benchmark_workload_256(precision):
+def test_benchmark_workload_256(precision, graph):
     w = workload("grf-256")
     box = _box(w["box"])
     rho = w["make"]()
-    got, used = gpu_solve(box, rho, w["shear"], precision, graph=True, autotune=True)
+    got, used = gpu_solve(box, rho, w["shear"], precision, graph=graph, autotune=True)
     err = rel_l2(got[0], oracle_solve(box, used[0], w["shear"]))
-    print(f"grf-256 {precision}: rel-L2 {err:.3e}")
+    print(f"grf-256 {precision} {'graph' if graph else 'direct'}: rel-L2 {err:.3e}")
     assert err <= TOL[precision], err
 
 
@@ -53,12 +54,13 @@ def test_lognormal_128_fp32():
     assert err <= TOL["fp32"], err
 
 
-def test_batch_of_64_uneven_boxes_fp32():
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+def test_batch_of_64_uneven_boxes_fp32(graph):
     ws = batch_workload()
     boxes = [_box(w["box"]) for w in ws]
     rhos = [w["make"]() for w in ws]
     shears = [w["shear"] for w in ws]
-    got, used = gpu_solve(boxes, rhos, shears, "fp32", graph=True, autotune=True)
+    got, used = gpu_solve(boxes, rhos, shears, "fp32", graph=graph, autotune=True)
     worst = 0.0
     for b, g, u, s in zip(boxes, got, used, shears):
         worst = max(worst, rel_l2(g, oracle_solve(b, u, s)))
