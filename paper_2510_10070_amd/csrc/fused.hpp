@@ -76,6 +76,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   constexpr int NT = fa_threads<V>();
   constexpr int PG = fa_pg<A, 4>();  // planes transformed side by side
   constexpr int TNT = NT / PG;       // threads per plane transform
+  // a transform owned by one wavefront needs no workgroup barrier between its stages
+  using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;        // output positions (ky, c) of one plane
   constexpr int POS = (QN + NT - 1) / NT;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
     constexpr bool lin = LIN;  // linear remap (one instantiation each: the spectral path keeps its registers)
     YInterp yi;
     if (lin) yi.init(-br->shy * (x + 0.5), NY);
-    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true>(
+    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(
         mytile, TwS<T>{tw}, stid,
         [&](int e, int c) {
           cplx<T> v = mk<T>(T(0), T(0));
@@ -223,6 +225,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   constexpr int NT = fa_threads<V>();
   constexpr int PG = fa_pg<A, 4>();
   constexpr int TNT = NT / PG;
+  // a transform owned by one wavefront needs no workgroup barrier between its stages
+  using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;
   constexpr int POS = (QN + NT - 1) / NT;
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
         store(e, c, yi.sample<T>(e, NY, [&](int y) { return mytile[L::at(y, c)]; }));
       }
     } else {
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false, 0, 1, Sy>(
           mytile, TwS<T>{tw}, stid, [&](int e, int c) { return mytile[L::at(e, c)]; }, store);
     }
     __syncthreads();  // the tiles are rebuilt for the next planes
