@@ -254,6 +254,7 @@ template <int NB_, int LD_, int BS_, bool BFAST_> struct Tile {
 // conflicts, where the strided plain table has up to 8-way conflicts), and the r offsets are
 // compile-time constants.
 template <typename T> struct TwS {
+  static constexpr bool kInRegisters = false;
   const cplx<T>* p;
   __device__ __forceinline__ cplx<T> at(int i) const { return p[i]; }
 };
@@ -261,6 +262,7 @@ template <typename T> struct TwS {
 // 8 (N - 1) + 8 logical elements or more has room for it, and its stride-9 reads are
 // conflict-free as well.
 template <typename T> struct TwH {
+  static constexpr bool kInRegisters = false;
   const cplx<T>* tile;
   __device__ __forceinline__ cplx<T> at(int i) const { return tile[9 * i + 8]; }
 };
@@ -337,6 +339,8 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
             cplx<T> t;
             if constexpr (std::is_pointer_v<TW>)
               t = tw[k * r * (N / (NS * R))];
+            else if constexpr (TW::kInRegisters)
+              t = tw.template stage<S, NS>(r, k);
             else
               t = tw.at(NS - 1 + (r - 1) * NS + k);
             v[p][r] = D < 0 ? cmul<T>(v[p][r], t) : cmulc<T>(v[p][r], t);
@@ -388,6 +392,35 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
         }
       }
     }
+  }
+};
+
+// The twiddles one thread needs, held in registers: for a schedule RL whose stages give every
+// thread one butterfly (PER == 1), the thread's twiddle index k of each stage is fixed, so the
+// R - 1 twiddles of stages FIRST.. can be fetched once from the stage-major table `src` and reused
+// by every transform the thread runs with that schedule; earlier stages still read `src`.
+template <typename T, int N, class RL, class L, int NT, class SRC, int FIRST = 1> struct TwReg {
+  static constexpr bool kInRegisters = true;
+  SRC src;
+  cplx<T> w[RL::n][8];
+  __device__ __forceinline__ void load(int tid) { load_stage<FIRST>(tid); }
+  template <int S> __device__ __forceinline__ void load_stage(int tid) {
+    if constexpr (S < RL::n) {
+      using St = Stage<T, N, RL, S, L, NT, -1>;
+      static_assert(St::PER == 1, "one butterfly per thread and stage");
+      int j, b;
+      St::item(tid, 0, j, b);
+      const int k = j % St::NS;
+#pragma unroll
+      for (int r = 1; r < St::R; ++r) w[S][r] = src.at(St::NS - 1 + (r - 1) * St::NS + k);
+      load_stage<S + 1>(tid);
+    }
+  }
+  template <int S, int NS> __device__ __forceinline__ cplx<T> stage(int r, int k) const {
+    if constexpr (S >= FIRST)
+      return w[S][r];
+    else
+      return src.at(NS - 1 + (r - 1) * NS + k);
   }
 };
 

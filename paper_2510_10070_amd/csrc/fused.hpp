@@ -617,8 +617,18 @@ template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves
 template <int M, int B, int Q> constexpr bool fb_tw_in_holes() {
   return same_schedule<typename Fwd<M>::L, typename Inv<M>::L>() && B * (M / Q) >= 8 * (M - 1) + 8;
 }
+// Float plans whose schedule gives each lane one butterfly per stage (M = 512) keep the lane's
+// twiddles in registers instead (pass B is bound by LDS issue, and those reads are the same for
+// every pencil): the extra registers cost one block per CU, which measured as the better trade.
+template <typename T, int M, int B, int Q> constexpr bool fb_tw_in_registers() {
+  using S0 = Stage<T, M, typename Fwd<M>::L, 0, Tile<fb_pw<M, B, Q>(), 1, M, false>, 64, -1>;
+  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && S0::PER == 1;
+}
 template <typename T, int M, int B, int Q> constexpr int fb_waves_per_eu() {
-  return (sizeof(T) == 4 && fb_tw_in_holes<M, B, Q>()) ? 4 : 1;
+  if constexpr (fb_tw_in_registers<T, M, B, Q>())
+    return 3;
+  else
+    return (sizeof(T) == 4 && fb_tw_in_holes<M, B, Q>()) ? 4 : 1;
 }
 
 template <typename T, int M, int B, int Q> struct FbShared {
@@ -748,6 +758,10 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
   const bool own0 = it.own0;
   const int wave = tid >> 6, lane = tid & 63;
   cplx<T>* tile = sh.tile;
+  // the lane's twiddles, the same for every pencil, read from LDS once when registers allow
+  constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
+  TwReg<T, M, RF, LW, 64, decltype(fb_twf(sh))> twr{fb_twf(sh)};
+  if constexpr (kTwReg) twr.load(lane);
   // the z-table rows of this lane's spectrum elements: the same for every pencil it transforms
   constexpr int NSL = spectrum_slots<T, M, LW, 64>();
   ZRow<T> zr[NSL];
@@ -778,7 +792,9 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
       __builtin_amdgcn_sched_barrier(0);  // one transform at a time (register pressure)
       const int kq = k0 + q * PW;
       fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-          area, fb_twf(sh), fb_twi(sh), lane, [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
+          area, [&] { if constexpr (kTwReg) return twr; else return fb_twf(sh); }(),
+          [&] { if constexpr (kTwReg) return twr; else return fb_twi(sh); }(), lane,
+          [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
           [&](int, int p, cplx<T>& v, int i) {
             const int k2 = kq + p;
             const T gk = green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zr[i]);
