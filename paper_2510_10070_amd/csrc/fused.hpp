@@ -223,7 +223,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = fa_threads<V>();
-  constexpr int PG = fa_pg<A, 4>();
+  // 32-byte rows with Ny <= 256: eight planes at a time, one wavefront per plane transform
+  constexpr int PG = fa_pg<A, (V == 0 && NY <= 256) ? 8 : 4>();
   constexpr int TNT = NT / PG;
   // a transform owned by one wavefront needs no workgroup barrier between its stages
   using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;

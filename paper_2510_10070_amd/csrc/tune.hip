@@ -19,9 +19,9 @@ namespace sbp {
 void default_variants(int prec, const BoxGeom& g, int var[kKinds]) {
   for (int k = 0; k < 5; ++k) var[k] = 1;
   for (int k = 5; k < kKinds; ++k) var[k] = 0;
-  // float pass C in half-size blocks with 16-byte rows: two blocks per CU at its register count
-  if (prec && g.ny <= 256) var[kFC] = 2;
-  // double passes A and C with the z columns of a position split over a lane pair
+  // float passes A and C keep 32-byte rows (variant 0; pass C then transforms eight planes at a
+  // time, one wavefront each, where Ny <= 256); double passes A and C split the z columns of a
+  // position over a lane pair
   if (!prec && g.ny <= 256) var[kFA] = var[kFC] = 3;
 }
 
