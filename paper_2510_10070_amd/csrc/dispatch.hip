@@ -1,4 +1,6 @@
 // Precision dispatch of the pass launchers (no kernels are instantiated here).
+#include <cstring>
+
 #include "fused.hpp"
 
 namespace sbp {
@@ -74,6 +76,34 @@ __global__ __launch_bounds__(256) void k_fetch(const BoxRec* __restrict__ ring, 
   }
 }
 static_assert(sizeof(BoxRec) % sizeof(uint2) == 0, "records are copied as 8-byte words");
+
+// Direct launches of plans with few boxes pass the records by value: the kernel arguments reach
+// device memory with the launch, so the copy needs no read of host memory across PCIe.
+template <int N> struct RecArgs {
+  BoxRec r[N];
+};
+template <int N>
+__global__ __launch_bounds__(256) void k_fetch_args(RecArgs<N> in, BoxRec* __restrict__ recs, int nrec) {
+  constexpr int W = sizeof(BoxRec) / sizeof(uint2);
+  const uint2* src = reinterpret_cast<const uint2*>(in.r);
+  uint2* dst = reinterpret_cast<uint2*>(recs);
+  for (int i = threadIdx.x; i < nrec * W; i += blockDim.x) dst[i] = src[i];
+}
+template <int N> hipError_t fetch_args_n(const BoxRec* host, BoxRec* recs, int nrec, hipStream_t st) {
+  RecArgs<N> in;
+  std::memcpy(in.r, host, sizeof(BoxRec) * nrec);
+  std::memset(in.r + nrec, 0, sizeof(BoxRec) * (N - nrec));
+  hipLaunchKernelGGL(k_fetch_args<N>, dim3(1), dim3(256), 0, st, in, recs, nrec);
+  return hipGetLastError();
+}
+
+hipError_t launch_fetch_args(const BoxRec* host, BoxRec* recs, int nrec, hipStream_t st) {
+  if (nrec <= 1) return fetch_args_n<1>(host, recs, nrec, st);
+  if (nrec <= 2) return fetch_args_n<2>(host, recs, nrec, st);
+  if (nrec <= 4) return fetch_args_n<4>(host, recs, nrec, st);
+  if (nrec <= kArgRecs) return fetch_args_n<kArgRecs>(host, recs, nrec, st);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_fetch(const BoxRec* ring, BoxRec* recs, int nrec, int nslots, int slot, int* ctl, hipStream_t st) {
   const size_t words = (size_t)nrec * (sizeof(BoxRec) / sizeof(uint2));

@@ -101,6 +101,9 @@ hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, 
 // Copy the records of one solve from pinned ring slot `slot` (or, with slot < 0, from the slot
 // named by ctl[0], which the kernel then advances) into the device record array.
 hipError_t launch_fetch(const BoxRec* ring, BoxRec* recs, int nrec, int nslots, int slot, int* ctl, hipStream_t st);
+// records of at most kArgRecs boxes passed as kernel arguments (direct launches)
+constexpr int kArgRecs = 8;
+hipError_t launch_fetch_args(const BoxRec* host, BoxRec* recs, int nrec, hipStream_t st);
 
 // Output for the hydrodynamics: vertical ghost layers and the acceleration (gravity.hip).
 hipError_t launch_ghosts(int prec, const BoxGeom& g, const void* phi, void* out, int ng, hipStream_t st);

@@ -396,12 +396,16 @@ hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
   }
 }
 
-// launch one solve: the record fetch, then the passes.  fetch_slot < 0: the slot comes from the
-// device-side ring counter (graph capture).
-sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot) {
+// launch one solve: the record fetch, then the passes.  Records come from `arg_recs` (host
+// memory, passed as kernel arguments) when given, else from ring slot fetch_slot, or, when
+// fetch_slot < 0, from the slot named by the device-side ring counter (graph capture).
+sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot, const sbp::BoxRec* arg_recs = nullptr) {
   const char* T = p->d_tables;
   if (mk) mk->mark("records");
-  HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
+  if (arg_recs)
+    HIP_TRY(sbp::launch_fetch_args(arg_recs, p->d_recs, (int)p->nrec, st));
+  else
+    HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
   if (p->flags & SBP_FLAG_PLAIN) {
     const BoxInfo& bi = p->boxes[0];
     sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1};
@@ -440,12 +444,8 @@ void bind_workspace(sbp_plan p) {
   for (size_t b = 0; b < p->boxes.size(); ++b) p->master[b].W = p->ws + p->boxes[b].ws_off;
 }
 
-// fill the next ring slot with the records of one solve (the fetch kernel copies it to the
-// device); waits only if that slot's previous solve has not yet been fetched
-sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, int* slot_out) {
-  const int slot = p->slot;
-  if (p->slot_used[slot]) HIP_TRY(hipEventSynchronize(p->slot_ev[slot]));
-  sbp::BoxRec* hs = p->h_stage + (size_t)slot * p->nrec;
+// the records of one solve: the plan's templates with the per-solve fields filled in
+void fill_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, sbp::BoxRec* hs) {
   for (size_t r = 0; r < p->nrec; ++r) {
     const size_t b = (p->flags & SBP_FLAG_PLAIN) ? 0 : r;
     hs[r] = p->master[r];
@@ -462,6 +462,14 @@ sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, c
     hs[r].fourpiG = 4.0 * M_PI * s.G;
     hs[r].scale = hs[r].fourpiG / ((double)g.nx * g.ny * g.m);
   }
+}
+
+// fill the next ring slot with the records of one solve (the fetch kernel copies it to the
+// device); waits only if that slot's previous solve has not yet been fetched
+sbp_status stage_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, int* slot_out) {
+  const int slot = p->slot;
+  if (p->slot_used[slot]) HIP_TRY(hipEventSynchronize(p->slot_ev[slot]));
+  fill_records(p, rho, phi, params, p->h_stage + (size_t)slot * p->nrec);
   *slot_out = slot;
   return SBP_OK;
 }
@@ -890,6 +898,13 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
       const int zero[2] = {0, 0};
       HIP_TRY(hipMemcpy(p->d_ctl, zero, sizeof zero, hipMemcpyHostToDevice));
       p->slot = 0;
+    }
+    if (!(p->flags & SBP_FLAG_GRAPH) && p->nrec <= (size_t)sbp::kArgRecs) {
+      // direct launches of a small plan: the records travel as kernel arguments, no ring slot
+      sbp::BoxRec recs[sbp::kArgRecs];
+      fill_records(p, rho, phi, params, recs);
+      Marker mk{p, st};
+      return enqueue(p, st, p->prof ? &mk : nullptr, 0, recs);
     }
     int slot = 0;
     sbp_status ss = stage_records(p, rho, phi, params, &slot);
