@@ -116,9 +116,12 @@ __device__ __forceinline__ int find_box(gmem<const int>* __restrict__ starts, in
 
 // locate this block's box and its tile index within the box (XCD-aware order over the launch)
 __device__ __forceinline__ const BoxRec* group_box(const GroupArgs& ga, const BoxRec* __restrict__ recs, int& tile) {
+  const int b = xcd_tile(blockIdx.x, ga.total);
+  if (ga.n == 1) {
+    tile = b;
+    return recs + ga.box0;
+  }
   gmem<const int>* starts = hbm(ga.starts);
-  const int total = starts[ga.n];
-  const int b = xcd_tile(blockIdx.x, total);
   const int i = find_box(starts, ga.n, b);
   tile = b - starts[i];
   return recs + hbm(ga.box_ids)[i];

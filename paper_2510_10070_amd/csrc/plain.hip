@@ -223,6 +223,8 @@ hipError_t launch_plain(const BoxRec* h_rec, const BoxRec* rec, const BoxRec* pa
   // `one`: box ids {0}; starts {0, y blocks} at [0..1] and {0, x blocks} at [2..3]
   GroupArgs gy = one, gx = one;
   gx.starts = one.starts + 2;
+  gy.total = yb;
+  gx.total = xb;
   if (g.method == 1) {
     PLAIN_STEP("plain_reduce", hipLaunchKernelGGL(k_plain_reduce, dim3(kPlainPartials), dim3(kEw), 0, st, rec));
     PLAIN_STEP("plain_coef", hipLaunchKernelGGL(k_plain_coef, dim3(1), dim3(64), 0, st, rec));

@@ -62,6 +62,8 @@ struct GroupArgs {
   const int* box_ids;  // boxes of the group (indices into the BoxRec array)
   const int* starts;   // first block of each box; starts[n] = total blocks
   int n;
+  int total;           // = starts[n], the launch's block count
+  int box0;            // = box_ids[0]: a one-box group needs no table lookup
 };
 
 // Supported transform lengths (x, y and padded z).

@@ -378,7 +378,7 @@ void build_launches(sbp_plan p) {
 
 hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
   const char* T = p->d_tables;
-  sbp::GroupArgs ga{p->d_ints + l.ints_off, p->d_ints + l.ints_off + l.n, l.n};
+  sbp::GroupArgs ga{p->d_ints + l.ints_off, p->d_ints + l.ints_off + l.n, l.n, l.blocks, p->ints[l.ints_off]};
   switch (l.kind) {
     case sbp::kYFwd:
       return sbp::launch_y(p->prec, true, true, l.len, l.variant, ga, l.blocks, p->d_recs, T + l.tw, st);
@@ -408,7 +408,7 @@ sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot, const
     HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
   if (p->flags & SBP_FLAG_PLAIN) {
     const BoxInfo& bi = p->boxes[0];
-    sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1};
+    sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1, 0, 0};
     HIP_TRY(sbp::launch_plain(&p->master[0], p->d_recs, p->d_recs + 1, one, bi.var[sbp::kYFwd], bi.var[sbp::kXFwd],
                               T + bi.tws_x, T + bi.tws_y, T + bi.tw_m, st, mk ? mark_cb : nullptr, mk));
     return SBP_OK;
