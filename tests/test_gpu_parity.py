@@ -181,6 +181,35 @@ def test_graph_replay_with_new_pointers():
     ref_plan.close()
 
 
+@pytest.mark.parametrize("nbox", [8, 9])
+def test_record_delivery_direct(nbox):
+    # direct launches: plans of up to 8 boxes pass each solve's records as kernel arguments,
+    # larger plans stage them in a pinned ring of 64 slots.  70 solves wrap the ring; each
+    # changes every box's shear time and alternates between two output sets, so the last two
+    # solves (different records) are both checked against the oracle.
+    import torch
+
+    from paper_2510_10070_amd import Box, Plan, Shear
+
+    shapes = [(16, 16, 16) if i % 2 else (32, 16, 16) for i in range(nbox)]
+    boxes = [_box(s + (1.0, 1.0 + 0.05 * i, 1.0, 2, 0.0), "sasha" if i % 3 == 2 else "vgf")
+             for i, s in enumerate(shapes)]
+    rhos = [lognormal_density(s, 0.8, 0.2, seed=90 + i) for i, s in enumerate(shapes)]
+    plan = Plan([Box(**b) for b in boxes], precision="fp64")
+    r_t = [torch.tensor(r, dtype=torch.float64, device="cuda:0") for r in rhos]
+    outs = [[torch.empty_like(r) for r in r_t] for _ in range(2)]
+    shear = lambda k, i: (1.5, 1.0, 0.01 * k + 0.1 * i, 1.0 + 0.01 * i)
+    nsolve = 70
+    for k in range(nsolve):
+        plan.solve(r_t, outs[k % 2], [Shear(*shear(k, i)) for i in range(nbox)])
+    torch.cuda.synchronize()
+    for k in (nsolve - 2, nsolve - 1):
+        for i, b in enumerate(boxes):
+            got = outs[k % 2][i].cpu().numpy()
+            assert rel_l2(got, oracle_solve(b, rhos[i], shear(k, i))) <= TOL["fp64"], (k, i)
+    plan.close()
+
+
 # shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 8, 16}, y up to 512,
 # padded z from 32 to 512, P = 4 (power-of-two padded z lengths leave no ragged z chunk)
 FUSED_SHAPES = [
