@@ -614,7 +614,7 @@ template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves
 
 // Twiddles: the stage-major table of the forward schedule of M, then that of the inverse one if
 // it differs.  When one table serves both and the tile's spare pad8 slots can hold it, it lives
-// there (TwH): the block then fits four to a CU in float.
+// there (TwH), which keeps pass B's LDS small enough for four blocks per CU in float.
 template <int M, int B, int Q> constexpr bool fb_tw_in_holes() {
   return same_schedule<typename Fwd<M>::L, typename Inv<M>::L>() && B * (M / Q) >= 8 * (M - 1) + 8;
 }
@@ -798,7 +798,10 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
           [&](int, int, int i) { return in[q][i / S0::R][i % S0::R]; },
           [&](int, int p, cplx<T>& v, int i) {
             const int k2 = kq + p;
-            const T gk = green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zr[i]);
+            // float: the k = 0 pencil (own0) is neither read nor written back here
+            const T gk = FbShared<T, M, B, Q>::kF32
+                             ? green_at_nonzero(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], zr[i])
+                             : green_at(sh.pa0[k2], sh.pe[k2], sh.pik[k2], sh.pk2[k2], sh.psp[k2], zr[i]);
             v.x *= gk;
             v.y *= gk;
           },

@@ -73,6 +73,12 @@ __device__ __forceinline__ T green_at(T a0, T e, T ik, T k2, T zero, const ZRow<
   const T gk = -(a0 + e * (zr.s2 + ik * zr.ks)) * fast_rcp(den);
   return den == T(0) ? zero : gk;
 }
+// The same where the element with a zero denominator (Kx = Ky = kz = 0) is never used: float
+// plans take the whole k = 0 pencil in double apart from the transforms.
+template <typename T>
+__device__ __forceinline__ T green_at_nonzero(T a0, T e, T ik, T k2, const ZRow<T>& zr) {
+  return -(a0 + e * (zr.s2 + ik * zr.ks)) * fast_rcp(k2 + zr.kz2);
+}
 
 constexpr int kPassThreads = 256;
 

@@ -24,7 +24,8 @@ struct SashaCoef {
 };
 
 // Everything a kernel needs about one box, in device memory.  The per-solve fields are
-// rewritten by one host-to-device copy per solve (also under graph replay).
+// rewritten by the first kernel of every solve (also under graph replay), from the solve's
+// kernel arguments or from a pinned ring slot.
 struct BoxRec {
   BoxGeom g;
   // per solve
