@@ -43,6 +43,7 @@ hipError_t launch_ac_ny(int kind, int a, int variant, bool lin, GroupArgs ga, in
 #define SBP_AC(A_)                                                                                                \
   if (a == A_) {                                                                                                  \
     if (variant >= 2) return launch_ac_narrow<T, NY, A_, B>(kind, variant, lin, blocks, ga, recs, t1, t2, st);  \
+    if (variant != 0) return hipErrorInvalidValue; /* the grid was sized for that variant's tiles */           \
     if (kind == 0) {                                                                                              \
       if (lin) hipLaunchKernelGGL((k_fa<T, NY, A_, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2); \
       else hipLaunchKernelGGL((k_fa<T, NY, A_, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);   \
