@@ -398,7 +398,8 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
 // The twiddles one thread needs, held in registers: for a schedule RL whose stages give every
 // thread one butterfly (PER == 1), the thread's twiddle index k of each stage is fixed, so the
 // R - 1 twiddles of stages FIRST.. can be fetched once from the stage-major table `src` and reused
-// by every transform the thread runs with that schedule; earlier stages still read `src`.
+// by every transform the thread runs with that schedule; earlier stages still read `src`.  An
+// inverse transform may use the same object when its schedule equals RL (the stages conjugate).
 template <typename T, int N, class RL, class L, int NT, class SRC, int FIRST = 1> struct TwReg {
   static constexpr bool kInRegisters = true;
   SRC src;
@@ -408,6 +409,7 @@ template <typename T, int N, class RL, class L, int NT, class SRC, int FIRST = 1
     if constexpr (S < RL::n) {
       using St = Stage<T, N, RL, S, L, NT, -1>;
       static_assert(St::PER == 1, "one butterfly per thread and stage");
+      static_assert(St::R <= 8, "radix above the register table");
       int j, b;
       St::item(tid, 0, j, b);
       const int k = j % St::NS;

@@ -41,6 +41,23 @@ template <int A, int CAP> constexpr int fa_pg() {
   return p;
 }
 
+// LDS of a pass-A (C = false) or pass-C (C = true) block for tile variant V (0..2)
+template <typename T, int NY, int A, int V, bool C> struct AcShape {
+  static constexpr int NB = fa_zc<T, V>() / 2;
+  static constexpr int NT = fa_threads<V>();
+  // pass C with 32-byte rows and Ny <= 256: eight planes at a time, one wavefront per plane
+  static constexpr int PG = C ? fa_pg<A, (V == 0 && NY <= 256) ? 8 : 4>() : fa_pg<A, 4>();
+  static constexpr int TILE = PG * lds_slots(NY * NB);  // PG plane tiles
+};
+// the largest tile over A in {1, 2, 4, 6, 8} (launch groups that mix Nx)
+template <typename T, int NY, int V, bool C> constexpr int ac_mix_tile() {
+  constexpr int t[5] = {AcShape<T, NY, 1, V, C>::TILE, AcShape<T, NY, 2, V, C>::TILE, AcShape<T, NY, 4, V, C>::TILE,
+                        AcShape<T, NY, 6, V, C>::TILE, AcShape<T, NY, 8, V, C>::TILE};
+  int m = 0;
+  for (int v : t) m = v > m ? v : m;
+  return m;
+}
+
 // remap phase of plane x = j + B a as P_j Q^a in double: exp(-i 2 pi my (2x+1) fy)
 struct PlanePhase {
   double pr, pi, qr, qi;  // current phase and the per-plane step
@@ -69,12 +86,12 @@ struct PlanePhase {
 // A-point DFT across planes, the w_Nx^(j k1) twiddle and the store to W[k1][my][j][z].
 
 template <typename T, int NY, int A, int B, int V, bool LIN>
-__global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                                 const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+__device__ __forceinline__ void fa_body(const BoxRec* br, int t, const cplx<T>* __restrict__ twy,
+                                        const cplx<T>* __restrict__ twx, cplx<T>* tile, cplx<T>* tw, double* red) {
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = fa_threads<V>();
-  constexpr int PG = fa_pg<A, 4>();  // planes transformed side by side
+  constexpr int PG = AcShape<T, NY, A, V, false>::PG;  // planes transformed side by side
   constexpr int TNT = NT / PG;       // threads per plane transform
   // a transform owned by one wavefront needs no workgroup barrier between its stages
   using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
@@ -83,12 +100,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   constexpr int POS = (QN + NT - 1) / NT;
   constexpr int SLOTS = lds_slots(NY * NB);
   using L = Tile<NB, NB, 1, true>;
-  __shared__ cplx<T> tile[PG * SLOTS];
-  __shared__ cplx<T> tw[NY];
-  __shared__ double red[2][NT / 64];
 
-  int t;
-  const BoxRec* br = group_box(ga, recs, t);
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
   const int sub = tid / TNT, stid = tid - sub * TNT;
@@ -167,15 +179,15 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
       s1 += __shfl_down(s1, o);
     }
     if ((tid & 63) == 0) {
-      red[0][tid >> 6] = s0;
-      red[1][tid >> 6] = s1;
+      red[tid >> 6] = s0;
+      red[NT / 64 + (tid >> 6)] = s1;
     }
     __syncthreads();
     if (tid == 0) {
       double sa = 0.0, sb = 0.0;
       for (int i = 0; i < NT / 64; ++i) {
-        sa += red[0][i];
-        sb += red[1][i];
+        sa += red[i];
+        sb += red[NT / 64 + i];
       }
       hbm(br->partials)[2 * t] = sa;
       hbm(br->partials)[2 * t + 1] = sb;
@@ -212,19 +224,52 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   }
 }
 
+template <typename T, int NY, int A, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                 const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+  using S = AcShape<T, NY, A, V, false>;
+  __shared__ cplx<T> tile[S::TILE];
+  __shared__ cplx<T> tw[NY];
+  __shared__ double red[2 * (S::NT / 64)];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  fa_body<T, NY, A, B, V, LIN>(br, t, twy, twx, tile, tw, red);
+}
+
+// Pass A for a launch group whose boxes differ in Nx = B A (A <= 8): every block runs the body
+// of its own box's A with that box's x twiddles, so one launch covers what would otherwise be
+// one small launch per A.  Registers and LDS are those of the largest body.
+template <typename T, int NY, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fa_mix(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                     const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
+  constexpr int NT = fa_threads<V>();
+  __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, false>()];
+  __shared__ cplx<T> tw[NY];
+  __shared__ double red[2 * (NT / 64)];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const cplx<T>* twx = static_cast<const cplx<T>*>(br->twx);
+  switch (br->g.nx / B) {
+    case 1: fa_body<T, NY, 1, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
+    case 2: fa_body<T, NY, 2, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
+    case 4: fa_body<T, NY, 4, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
+    case 6: fa_body<T, NY, 6, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
+    default: fa_body<T, NY, 8, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Pass C: inverse of pass A.  Load W[k1][my][j][z chunk] for all k1, conjugate twiddle,
 // A-point inverse DFT across k1 in registers, then per plane: reverse remap, Hermitian columns
 // in LDS, inverse y transform straight to phi (+ Phi_0 for SASHA).
 
 template <typename T, int NY, int A, int B, int V, bool LIN>
-__global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                                 const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+__device__ __forceinline__ void fc_body(const BoxRec* br, int t, const cplx<T>* __restrict__ twy,
+                                        const cplx<T>* __restrict__ twx, cplx<T>* tile, cplx<T>* tw) {
   constexpr int ZC = fa_zc<T, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = fa_threads<V>();
-  // 32-byte rows with Ny <= 256: eight planes at a time, one wavefront per plane transform
-  constexpr int PG = fa_pg<A, (V == 0 && NY <= 256) ? 8 : 4>();
+  constexpr int PG = AcShape<T, NY, A, V, true>::PG;
   constexpr int TNT = NT / PG;
   // a transform owned by one wavefront needs no workgroup barrier between its stages
   using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
@@ -233,11 +278,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
   constexpr int POS = (QN + NT - 1) / NT;
   constexpr int SLOTS = lds_slots(NY * NB);
   using L = Tile<NB, NB, 1, true>;
-  __shared__ cplx<T> tile[PG * SLOTS];
-  __shared__ cplx<T> tw[NY];
 
-  int t;
-  const BoxRec* br = group_box(ga, recs, t);
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
   const int sub = tid / TNT, stid = tid - sub * TNT;
@@ -356,6 +397,34 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
           mytile, TwS<T>{tw}, stid, [&](int e, int c) { return mytile[L::at(e, c)]; }, store);
     }
     __syncthreads();  // the tiles are rebuilt for the next planes
+  }
+}
+
+template <typename T, int NY, int A, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                 const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
+  __shared__ cplx<T> tile[AcShape<T, NY, A, V, true>::TILE];
+  __shared__ cplx<T> tw[NY];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  fc_body<T, NY, A, B, V, LIN>(br, t, twy, twx, tile, tw);
+}
+
+// Pass C for a launch group whose boxes differ in Nx (A <= 8), as k_fa_mix
+template <typename T, int NY, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                     const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
+  __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, true>()];
+  __shared__ cplx<T> tw[NY];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const cplx<T>* twx = static_cast<const cplx<T>*>(br->twx);
+  switch (br->g.nx / B) {
+    case 1: fc_body<T, NY, 1, B, V, LIN>(br, t, twy, twx, tile, tw); break;
+    case 2: fc_body<T, NY, 2, B, V, LIN>(br, t, twy, twx, tile, tw); break;
+    case 4: fc_body<T, NY, 4, B, V, LIN>(br, t, twy, twx, tile, tw); break;
+    case 6: fc_body<T, NY, 6, B, V, LIN>(br, t, twy, twx, tile, tw); break;
+    default: fc_body<T, NY, 8, B, V, LIN>(br, t, twy, twx, tile, tw); break;
   }
 }
 
@@ -759,7 +828,8 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
   const bool own0 = it.own0;
   const int wave = tid >> 6, lane = tid & 63;
   cplx<T>* tile = sh.tile;
-  // the lane's twiddles, the same for every pencil, read from LDS once when registers allow
+  // the lane's twiddles, the same for every pencil, read from LDS once when registers allow (the
+  // inverse schedule equals the forward one wherever this applies: fb_tw_in_holes)
   constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
   TwReg<T, M, RF, LW, 64, decltype(fb_twf(sh))> twr{fb_twf(sh)};
   if constexpr (kTwReg) twr.load(lane);

@@ -345,6 +345,25 @@ void build_launches(sbp_plan p) {
       const int lin = (kind == sbp::kFA || kind == sbp::kFC) && bi.g.remap == SBP_REMAP_LINEAR;
       groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a, lin)].push_back(b);
     }
+    if ((kind == sbp::kFA || kind == sbp::kFC) && p->prec == SBP_FP32) {
+      // float passes A and C in 32-byte rows: groups that differ only in A <= 8 share one launch
+      // (k_fa_mix / k_fc_mix, a = 0), rather than one small launch each
+      std::map<std::tuple<int, int, int, int>, std::vector<std::tuple<int, int, int, int, int>>> same;
+      for (auto& kv : groups) {
+        const auto& [len, var, q, a, lin] = kv.first;
+        if (var == 0 && a >= 1 && a <= 8) same[std::make_tuple(len, var, q, lin)].push_back(kv.first);
+      }
+      for (auto& sv : same) {
+        if (sv.second.size() < 2) continue;
+        const auto& [len, var, q, lin] = sv.first;
+        std::vector<int>& merged = groups[std::make_tuple(len, var, q, 0, lin)];
+        for (const auto& key : sv.second) {
+          merged.insert(merged.end(), groups[key].begin(), groups[key].end());
+          groups.erase(key);
+        }
+        std::sort(merged.begin(), merged.end());
+      }
+    }
     for (auto& kv : groups) {
       Launch l;
       l.kind = kind;
@@ -784,6 +803,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       rec.coef = p->d_coef + b;
       rec.zt = p->d_tables + bi.zt;
       rec.k0h = (const double*)(p->d_tables + bi.k0h);
+      rec.twx = p->d_tables + bi.tw_x;
       for (int k = 0; k < 3; ++k) rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
     }
 

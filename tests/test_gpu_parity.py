@@ -210,6 +210,26 @@ def test_record_delivery_direct(nbox):
     plan.close()
 
 
+@pytest.mark.parametrize("remap", ["spectral", "linear"])
+def test_mixed_nx_launch_groups_fp32(remap):
+    # FP32 passes A and C run boxes that differ only in Nx = 16 A (A <= 8) in one launch each,
+    # every block taking its box's A and x twiddles from the record: one launch per pass, and
+    # every box matches the oracle
+    from paper_2510_10070_amd import Box, Plan
+
+    shapes = [(16, 16, 16), (32, 16, 16), (64, 16, 16), (96, 16, 16), (128, 16, 16), (32, 16, 16)]
+    boxes = [dict(_box(s + (1.0 + 0.1 * i, 1.0, 1.0, 2, 0.0), "sasha" if i % 2 else "vgf"), remap=remap)
+             for i, s in enumerate(shapes)]
+    plan = Plan([Box(**b) for b in boxes], precision="fp32", schedule="fused")
+    assert plan.describe()["launches"] == 3  # pass A, pass B (one M), pass C
+    plan.close()
+    rhos = [lognormal_density(s, 1.0, 0.2, seed=120 + i) for i, s in enumerate(shapes)]
+    shears = [(1.5, 1.0, 0.2 + 0.1 * i, 1.0) for i in range(len(shapes))]
+    got, used = gpu_solve(boxes, rhos, shears, "fp32", schedule="fused")
+    for b, g, u, s in zip(boxes, got, used, shears):
+        assert rel_l2(g, oracle_solve(b, u, s)) <= TOL["fp32"], b
+
+
 # shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 8, 16}, y up to 512,
 # padded z from 32 to 512, P = 4 (power-of-two padded z lengths leave no ragged z chunk)
 FUSED_SHAPES = [
