@@ -108,18 +108,6 @@ template <typename T, int M, int V> constexpr int z_pp() { return (kPassThreads 
 // ------------------------------------------------------------------------------------------
 // launch groups
 
-__device__ __forceinline__ int find_box(gmem<const int>* __restrict__ starts, int n, int blk) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (starts[mid] <= blk)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 // locate this block's box and its tile index within the box (XCD-aware order over the launch)
 __device__ __forceinline__ const BoxRec* group_box(const GroupArgs& ga, const BoxRec* __restrict__ recs, int& tile) {
   const int b = xcd_tile(blockIdx.x, ga.total);
@@ -127,10 +115,9 @@ __device__ __forceinline__ const BoxRec* group_box(const GroupArgs& ga, const Bo
     tile = b;
     return recs + ga.box0;
   }
-  gmem<const int>* starts = hbm(ga.starts);
-  const int i = find_box(starts, ga.n, b);
-  tile = b - starts[i];
-  return recs + hbm(ga.box_ids)[i];
+  const int2 e = hbm(ga.blk)[b];
+  tile = e.y;
+  return recs + e.x;
 }
 
 // remap phase exp(-i 2 pi c) for c = my*(2x+1)*fy cycles, evaluated in double

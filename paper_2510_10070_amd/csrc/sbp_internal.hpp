@@ -66,6 +66,7 @@ struct GroupArgs {
   int n;
   int total;           // = starts[n], the launch's block count
   int box0;            // = box_ids[0]: a one-box group needs no table lookup
+  const int2* blk;     // n > 1: (box id, tile) of every block b < total, so one load finds both
 };
 
 // Supported transform lengths (x, y and padded z).

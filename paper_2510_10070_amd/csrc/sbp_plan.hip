@@ -76,6 +76,9 @@ struct sbp_plan_s {
   double* d_partials = nullptr;
   int* d_ints = nullptr;
   size_t nints_cap = 0;
+  std::vector<int> blk;     // per-block (box id, tile) pairs of the multi-box launch groups
+  int2* d_blk = nullptr;    // device copy (own allocation)
+  size_t nblk_cap = 0;      // capacity of d_blk in pairs
   std::vector<sbp::BoxRec> master;  // record templates (plan constants filled in)
   size_t ws_need = 0;
   char* ws = nullptr;
@@ -329,6 +332,7 @@ bool kind_applies(const BoxInfo& bi, int kind) { return bi.fused ? kind >= sbp::
 void build_launches(sbp_plan p) {
   p->launches.clear();
   p->ints.clear();
+  p->blk.clear();
   const int nb = (int)p->boxes.size();
   for (int phase = 0; phase < 5; ++phase)
   for (int kind = 0; kind < sbp::kKinds; ++kind) {
@@ -380,6 +384,17 @@ void build_launches(sbp_plan p) {
         p->ints.push_back(acc);
       }
       l.blocks = acc;
+      if (l.n > 1) {
+        // (box id, tile) of every block, so that a block finds its box with one load
+        l.blk_off = p->blk.size() / 2;
+        for (int i = 0; i < l.n; ++i) {
+          const int nt = p->ints[l.ints_off + l.n + i + 1] - p->ints[l.ints_off + l.n + i];
+          for (int t = 0; t < nt; ++t) {
+            p->blk.push_back(kv.second[i]);
+            p->blk.push_back(t);
+          }
+        }
+      }
       const BoxInfo& b0 = p->boxes[kv.second[0]];
       switch (kind) {
         case sbp::kYFwd:
@@ -397,7 +412,8 @@ void build_launches(sbp_plan p) {
 
 hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
   const char* T = p->d_tables;
-  sbp::GroupArgs ga{p->d_ints + l.ints_off, p->d_ints + l.ints_off + l.n, l.n, l.blocks, p->ints[l.ints_off]};
+  sbp::GroupArgs ga{p->d_ints + l.ints_off, p->d_ints + l.ints_off + l.n, l.n, l.blocks, p->ints[l.ints_off],
+                    l.n > 1 ? p->d_blk + l.blk_off : nullptr};
   switch (l.kind) {
     case sbp::kYFwd:
       return sbp::launch_y(p->prec, true, true, l.len, l.variant, ga, l.blocks, p->d_recs, T + l.tw, st);
@@ -427,7 +443,7 @@ sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot, const
     HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
   if (p->flags & SBP_FLAG_PLAIN) {
     const BoxInfo& bi = p->boxes[0];
-    sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1, 0, 0};
+    sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1, 0, 0, nullptr};
     HIP_TRY(sbp::launch_plain(&p->master[0], p->d_recs, p->d_recs + 1, one, bi.var[sbp::kYFwd], bi.var[sbp::kXFwd],
                               T + bi.tws_x, T + bi.tws_y, T + bi.tw_m, st, mk ? mark_cb : nullptr, mk));
     return SBP_OK;
@@ -529,6 +545,18 @@ sbp_status upload_groups(sbp_plan p) {
   build_launches(p);
   if (p->ints.size() > p->nints_cap) return fail(SBP_E_STATE, "group table overflow");
   HIP_TRY(hipMemcpy(p->d_ints, p->ints.data(), p->ints.size() * sizeof(int), hipMemcpyHostToDevice));
+  // the per-block table (multi-box groups) grows with the tile variants the autotuner tries;
+  // it is only rebuilt while the plan is being created, before any solve uses it
+  if (p->blk.size() / 2 > p->nblk_cap) {
+    if (p->d_blk) HIP_TRY(hipFree(p->d_blk));
+    p->d_blk = nullptr;
+    p->nblk_cap = 0;
+    if (hipMalloc(&p->d_blk, p->blk.size() * sizeof(int)) != hipSuccess)
+      return fail(SBP_E_NOMEM, "block table allocation (%zu bytes)", p->blk.size() * sizeof(int));
+    p->nblk_cap = p->blk.size() / 2;
+  }
+  if (!p->blk.empty())
+    HIP_TRY(hipMemcpy(p->d_blk, p->blk.data(), p->blk.size() * sizeof(int), hipMemcpyHostToDevice));
   p->describe = describe_plan(p);
   return SBP_OK;
 }
@@ -1033,6 +1061,7 @@ sbp_status sbp_plan_destroy(sbp_plan p) {
   if (p->h_stage) hipHostFree(p->h_stage);
   if (p->ws_owned && p->ws) hipFree(p->ws);
   if (p->d_aux) hipFree(p->d_aux);
+  if (p->d_blk) hipFree(p->d_blk);
   if (p->d_tables) hipFree(p->d_tables);
   delete p;
   return SBP_OK;

@@ -22,6 +22,7 @@ struct Launch {
   bool lin = false;  // fused passes A and C: linear remap instantiation
   int blocks = 0;
   size_t ints_off = 0;  // offset (in ints) of box_ids[n] then starts[n+1] in the group int block
+  size_t blk_off = 0;   // n > 1: offset (in int2) of the per-block (box id, tile) table
   int n = 0;
   size_t tw = 0, tw64 = 0;  // table offsets
 };
