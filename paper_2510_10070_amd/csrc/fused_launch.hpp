@@ -35,7 +35,8 @@ hipError_t launch_ac_narrow(int kind, int variant, bool lin, int blocks, GroupAr
 }
 
 // passes A (kind 0) and C (kind 2) for one Ny, A = Nx/16 in {1, 2, 4, 6, 8, 16}, or a = 0 for a
-// group whose boxes have different A <= 8 (tile variant 0)
+// group whose boxes have different A <= 8; tile variant 1 (64-byte rows) only for float, A <= 8
+// and Ny <= 256
 template <typename T, int NY>
 hipError_t launch_ac_ny(int kind, int a, int variant, bool lin, GroupArgs ga, int blocks, const BoxRec* recs,
                         const cplx<T>* t1, const cplx<T>* t2, hipStream_t st) {
@@ -43,14 +44,14 @@ hipError_t launch_ac_ny(int kind, int a, int variant, bool lin, GroupArgs ga, in
   const dim3 grid(blocks);
   if (a == 0) {
     // a group that mixes Nx (A <= 8): each block takes its box's A and x twiddles from the record
-    if (variant != 0 || sizeof(T) != 4) return hipErrorInvalidValue;
-    if constexpr (sizeof(T) == 4) {
+    if (variant != 1 || sizeof(T) != 4 || NY > 256) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 4 && NY <= 256) {
     if (kind == 0) {
-      if (lin) hipLaunchKernelGGL((k_fa_mix<T, NY, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);
-      else hipLaunchKernelGGL((k_fa_mix<T, NY, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);
+      if (lin) hipLaunchKernelGGL((k_fa_mix<T, NY, B, 1, true>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2);
+      else hipLaunchKernelGGL((k_fa_mix<T, NY, B, 1, false>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2);
     } else {
-      if (lin) hipLaunchKernelGGL((k_fc_mix<T, NY, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);
-      else hipLaunchKernelGGL((k_fc_mix<T, NY, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);
+      if (lin) hipLaunchKernelGGL((k_fc_mix<T, NY, B, 1, true>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2);
+      else hipLaunchKernelGGL((k_fc_mix<T, NY, B, 1, false>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2);
     }
     }
     return hipGetLastError();
@@ -58,7 +59,19 @@ hipError_t launch_ac_ny(int kind, int a, int variant, bool lin, GroupArgs ga, in
 #define SBP_AC(A_)                                                                                                \
   if (a == A_) {                                                                                                  \
     if (variant >= 2) return launch_ac_narrow<T, NY, A_, B>(kind, variant, lin, blocks, ga, recs, t1, t2, st);  \
-    if (variant != 0) return hipErrorInvalidValue; /* the grid was sized for that variant's tiles */           \
+    if (variant == 1) {                                                                                           \
+      if constexpr (sizeof(T) == 4 && A_ <= 8 && NY <= 256) {                                                     \
+        if (kind == 0) {                                                                                          \
+          if (lin) hipLaunchKernelGGL((k_fa<T, NY, A_, B, 1, true>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2); \
+          else hipLaunchKernelGGL((k_fa<T, NY, A_, B, 1, false>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2);   \
+        } else {                                                                                                  \
+          if (lin) hipLaunchKernelGGL((k_fc<T, NY, A_, B, 1, true>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2); \
+          else hipLaunchKernelGGL((k_fc<T, NY, A_, B, 1, false>), grid, dim3(fa_threads<1>()), 0, st, ga, recs, t1, t2);   \
+        }                                                                                                         \
+        return hipGetLastError();                                                                                 \
+      }                                                                                                           \
+      return hipErrorInvalidValue; /* the grid was sized for that variant's tiles */                              \
+    }                                                                                                             \
     if (kind == 0) {                                                                                              \
       if (lin) hipLaunchKernelGGL((k_fa<T, NY, A_, B, 0, true>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2); \
       else hipLaunchKernelGGL((k_fa<T, NY, A_, B, 0, false>), grid, dim3(fa_threads<0>()), 0, st, ga, recs, t1, t2);   \

@@ -350,12 +350,12 @@ void build_launches(sbp_plan p) {
       groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a, lin)].push_back(b);
     }
     if ((kind == sbp::kFA || kind == sbp::kFC) && p->prec == SBP_FP32) {
-      // float passes A and C in 32-byte rows: groups that differ only in A <= 8 share one launch
-      // (k_fa_mix / k_fc_mix, a = 0), rather than one small launch each
+      // float passes A and C in 64-byte rows (A <= 8): groups that differ only in A share one
+      // launch (k_fa_mix / k_fc_mix, a = 0), rather than one small launch each
       std::map<std::tuple<int, int, int, int>, std::vector<std::tuple<int, int, int, int, int>>> same;
       for (auto& kv : groups) {
         const auto& [len, var, q, a, lin] = kv.first;
-        if (var == 0 && a >= 1 && a <= 8) same[std::make_tuple(len, var, q, lin)].push_back(kv.first);
+        if (var == 1 && a >= 1 && a <= 8) same[std::make_tuple(len, var, q, lin)].push_back(kv.first);
       }
       for (auto& sv : same) {
         if (sv.second.size() < 2) continue;

@@ -23,6 +23,9 @@ void default_variants(int prec, const BoxGeom& g, int var[kKinds]) {
   // time, one wavefront each, where Ny <= 256); double passes A and C split the z columns of a
   // position over a lane pair
   if (!prec && g.ny <= 256) var[kFA] = var[kFC] = 3;
+  // with A = Nx/16 <= 8 planes a thread holds half the spectra of A = 16 or less, which leaves room
+  // for 64-byte rows (variant 1): twice the z cells per block, half the blocks
+  if (prec && g.nx <= 128 && g.ny <= 256) var[kFA] = var[kFC] = 1;
 }
 
 namespace {
