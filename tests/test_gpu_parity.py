@@ -230,8 +230,9 @@ def test_mixed_nx_launch_groups_fp32(remap):
         assert rel_l2(g, oracle_solve(b, u, s)) <= TOL["fp32"], b
 
 
-# shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 8, 16}, y up to 512,
-# padded z from 32 to 512, P = 4 (power-of-two padded z lengths leave no ragged z chunk)
+# shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 6, 8, 16}, y up to
+# 512, padded z from 32 to 512 and 192, P in {2, 4}; float boxes with nx <= 128 and ny <= 256 take
+# 64-byte rows (16 z cells), so nz = 8 leaves a ragged tile
 FUSED_SHAPES = [
     (16, 16, 16, 1.0, 1.0, 1.0, 2, 0.0),
     (32, 64, 32, 1.2, 0.8, 1.0, 2, 0.0),
@@ -242,6 +243,7 @@ FUSED_SHAPES = [
     (16, 16, 256, 1.0, 1.0, 2.0, 2, 0.0),
     (96, 96, 96, 1.0, 1.5, 1.0, 2, 0.0),  # A = 6, Ny = 96, M = 192
     (96, 16, 32, 1.0, 1.0, 1.0, 2, 0.0),
+    (32, 32, 8, 1.0, 1.0, 0.5, 4, 0.0),  # fewer z cells than one 64-byte row: a ragged tile
 ]
 
 
