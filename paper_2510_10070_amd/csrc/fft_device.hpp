@@ -54,6 +54,12 @@ template <int D, typename T> __device__ __forceinline__ cplx<T> rot(cplx<T> a) {
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
 // LDS slots needed for a tile of n logical elements
 __host__ __device__ constexpr int lds_slots(int n) { return pad8(n - 1) + 1; }
+// Second padding (PAD = 1): three spare slots after every 32 logical elements.  For the 512-point
+// 8.8.8 exchange (stride-8 writes, stride-1 reads, 64-blocked stride-8 writes) it leaves a third of
+// pad8's LDS bank conflicts.
+__host__ __device__ constexpr int pad32x3(int i) { return i + 3 * (i >> 5); }
+template <int PAD> __host__ __device__ constexpr int pad_map(int i) { return PAD == 0 ? pad8(i) : pad32x3(i); }
+template <int PAD> __host__ __device__ constexpr int pad_slots(int n) { return pad_map<PAD>(n - 1) + 1; }
 // pad8(a + C) from pa = pad8(a): exact shift when C is a multiple of 8
 template <int C> __device__ __forceinline__ int pad_add(int pa, int a) {
   if constexpr (C % 8 == 0)
@@ -238,14 +244,17 @@ template <> struct Inv<768> { using L = RList<3, 4, 8, 8>; };
 template <> struct Fwd<1024> { using L = RList<8, 8, 4, 4>; };
 template <> struct Inv<1024> { using L = RList<4, 4, 8, 8>; };
 
-// Tile layout: NB transforms, element (j, b) at logical index j*LD + b*BS, LDS slot pad8(.).
-// BFAST selects which index consecutive threads walk (batch index for z-fastest tiles,
-// element index otherwise), so that neighbouring lanes touch neighbouring words.
-template <int NB_, int LD_, int BS_, bool BFAST_> struct Tile {
+// Tile layout: NB transforms, element (j, b) at logical index j*LD + b*BS, LDS slot
+// pad_map<PAD>(.) (PAD 0: pad8).  BFAST selects which index consecutive threads walk (batch index
+// for z-fastest tiles, element index otherwise), so that neighbouring lanes touch neighbouring
+// words.
+template <int NB_, int LD_, int BS_, bool BFAST_, int PAD_ = 0> struct Tile {
   static constexpr int NB = NB_, LD = LD_, BS = BS_;
   static constexpr bool BFAST = BFAST_;
+  static constexpr int PAD = PAD_;
   static __device__ __forceinline__ int logical(int j, int b) { return j * LD + b * BS; }
-  static __device__ __forceinline__ int at(int j, int b) { return pad8(j * LD + b * BS); }
+  static __device__ __forceinline__ int map(int i) { return pad_map<PAD>(i); }
+  static __device__ __forceinline__ int at(int j, int b) { return map(j * LD + b * BS); }
 };
 
 // Stage-major twiddle table of a schedule: stage S (Ns = product of the earlier radices, radix
@@ -311,7 +320,7 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
       int j, b;
       if (item(tid, p, j, b)) {
         const int a = L::logical(j, b);
-        const int pa = pad8(a);
+        const int pa = L::map(a);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[p][r] = buf[pad_off<NBF * L::LD>(pa, a, r)];
       }
@@ -319,10 +328,12 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
   }
   // stride-C offset r*C from the padded base
   template <int C> static __device__ __forceinline__ int pad_off(int pa, int a, int r) {
-    if constexpr (C % 8 == 0)
+    if constexpr (L::PAD == 0 && C % 8 == 0)
       return pa + r * (C + C / 8);
+    else if constexpr (L::PAD == 1 && C % 32 == 0)
+      return pa + r * (C + 3 * (C / 32));
     else
-      return pad8(a + r * C);
+      return L::map(a + r * C);
   }
   // tw: the plain table exp(-2 pi i m/N), m < N (a pointer), or the stage-major table of this
   // schedule (TwS)
@@ -377,18 +388,29 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
         const int k = j % NS;
         const int base = (j - k) * R + k;
         const int a = L::logical(base, b);
-        if constexpr ((NS * L::LD) % 8 == 0) {
+        if constexpr (L::PAD == 0 && (NS * L::LD) % 8 == 0) {
           const int pa = pad8(a);
 #pragma unroll
           for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + (NS * L::LD) / 8)] = v[p][r];
+        } else if constexpr (L::PAD == 1 && (NS * L::LD) % 32 == 0) {
+          const int pa = L::map(a);
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + 3 * ((NS * L::LD) / 32))] = v[p][r];
+        } else if constexpr (L::PAD == 1 && L::LD == 1 && 32 % NS == 0 && (NS * R) % 32 == 0 &&
+                             (L::BS % 32 == 0 || L::NB == 1)) {
+          // base mod 32 = k < NS and NS divides 32: output r crosses the same 32-blocks for
+          // every k, so its offset from the padded base is a constant
+          const int pa = L::map(a);
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[pa + r * NS + 3 * ((r * NS) >> 5)] = v[p][r];
         } else if constexpr (NS == 1 && R == 8 && L::LD == 1 && (L::BS % 8 == 0 || L::NB == 1)) {
-          // base = 8j: a multiple of 8, so the eight outputs share one pad shift
-          const int pa = pad8(a);
+          // base = 8j: a multiple of 8, so the eight outputs share one pad shift (both paddings)
+          const int pa = L::map(a);
 #pragma unroll
           for (int r = 0; r < R; ++r) buf[pa + r] = v[p][r];
         } else {
 #pragma unroll
-          for (int r = 0; r < R; ++r) buf[pad8(a + r * NS * L::LD)] = v[p][r];
+          for (int r = 0; r < R; ++r) buf[L::map(a + r * NS * L::LD)] = v[p][r];
         }
       }
     }

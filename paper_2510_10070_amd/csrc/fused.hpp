@@ -706,9 +706,13 @@ template <typename T, int M, int B, int Q> struct FbShared {
   static constexpr int NZ = M / Q;
   static constexpr bool kF32 = std::is_same<T, float>::value;
   static constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
-  static constexpr bool kHoles = fb_tw_in_holes<M, B, Q>();
-  cplx<T> tile[lds_slots(B * NZ)];
-  cplx<T> tw[kHoles ? 1 : kOneTw ? M : 2 * M];
+  // register twiddles (read once from HBM): the tile needs no twiddle slots, and at M = 512 it
+  // takes the padding with fewer bank conflicts in the 8.8.8 exchanges
+  static constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
+  static constexpr int PAD = (kTwReg && PW == 1 && M == 512) ? 1 : 0;
+  static constexpr bool kHoles = !kTwReg && fb_tw_in_holes<M, B, Q>();
+  cplx<T> tile[pad_slots<PAD>(B * NZ)];
+  cplx<T> tw[(kHoles || kTwReg) ? 1 : kOneTw ? M : 2 * M];
   T pa0[B], pe[B], pik[B], pk2[B], psp[B];  // Green's-function coefficients of the B modes
 };
 
@@ -795,7 +799,7 @@ template <typename T, int M, int B, int Q, int NT, class Src>
 __device__ __forceinline__ void fb_dft_in(FbShared<T, M, B, Q>& sh, int tid, Src&& src) {
   constexpr int NZ = M / Q;
   constexpr int ZPT = (NZ + NT - 1) / NT;
-  using LT = Tile<B, 1, NZ, false>;  // parked pencils: element z of pencil k2
+  using LT = Tile<B, 1, NZ, false, FbShared<T, M, B, Q>::PAD>;  // parked pencils: element z of pencil k2
 #pragma unroll
   for (int zi = 0; zi < ZPT; ++zi) {
     const int z = tid + zi * NT;
@@ -804,21 +808,25 @@ __device__ __forceinline__ void fb_dft_in(FbShared<T, M, B, Q>& sh, int tid, Src
 #pragma unroll
       for (int jj = 0; jj < B; ++jj) v[jj] = src(jj, z);
       Dft<B, -1, T>::run(v);
+      // NZ is a multiple of the padding period: pencil k2 starts k2 * map(NZ) slots further on
+      const int mz = LT::map(z);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) sh.tile[LT::at(z, k2)] = v[k2];
+      for (int k2 = 0; k2 < B; ++k2) sh.tile[mz + k2 * LT::map(NZ)] = v[k2];
     }
   }
 }
 
 // wavefront-private padded z transforms, Green multiply and inverse: Q groups per tile area
 template <typename T, int M, int B, int Q, int WV>
-__device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbItem<T>& it, int tid) {
+__device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbItem<T>& it, int tid,
+                                           const cplx<T>* __restrict__ twm) {
   constexpr int PW = fb_pw<M, B, Q>();
   constexpr int NTUP = fb_tuples<M, B, Q>();
   constexpr int NZ = M / Q;
   static_assert(Q * PW * NTUP == B, "groups must tile the B pencils");
-  using LT = Tile<B, 1, NZ, false>;
-  using LW = Tile<PW, 1, M, false>;  // one group's exchange layout inside its tuple's tile area
+  constexpr int PAD = FbShared<T, M, B, Q>::PAD;
+  using LT = Tile<B, 1, NZ, false, PAD>;
+  using LW = Tile<PW, 1, M, false, PAD>;  // one group's exchange layout inside its tuple's tile area
   using RF = typename Fwd<M>::L;
   using RI = typename Inv<M>::L;
   using S0 = Stage<T, M, RF, 0, LW, 64, -1>;
@@ -831,7 +839,7 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
   // the lane's twiddles, the same for every pencil, read from LDS once when registers allow (the
   // inverse schedule equals the forward one wherever this applies: fb_tw_in_holes)
   constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
-  TwReg<T, M, RF, LW, 64, decltype(fb_twf(sh))> twr{fb_twf(sh)};
+  TwReg<T, M, RF, LW, 64, TwS<T>> twr{TwS<T>{twm}};  // from the stage-major table in HBM
   if constexpr (kTwReg) twr.load(lane);
   // the z-table rows of this lane's spectrum elements: the same for every pencil it transforms
   constexpr int NSL = spectrum_slots<T, M, LW, 64>();
@@ -844,18 +852,30 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
       zr[i] = zrow(zt, mz < 0 ? 0 : mz);
     }
   }
+  const int mlane = LT::map(lane);
 #pragma unroll 1
   for (int tu = wave; tu < NTUP; tu += WV) {
     const int k0 = Q * PW * tu;  // first pencil of the tuple
-    cplx<T>* area = tile + pad8(k0 * NZ);  // Q * PW * NZ = PW * M logical slots
+    cplx<T>* area = tile + pad_map<PAD>(k0 * NZ);  // Q * PW * NZ = PW * M logical slots
     auto skip = [&](int k2) { return own0 && k2 == 0; };
     cplx<T> in[Q][S0::PER][S0::R];
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      S0::template read_fn<RIN>(in[q], lane, [&](int e, int p) {
-        const int k2 = k0 + q * PW + p;
-        return (e < NZ && !skip(k2)) ? tile[LT::at(e, k2)] : mk<T>(T(0), T(0));
-      });
+    for (int q = 0; q < Q; ++q) {
+      if constexpr (PAD == 1) {
+        // one pencil per transform and e = lane + 64 r: slot map(lane) + r map(64) in its pencil
+        static_assert(PW == 1 && S0::NBF == 64 && S0::PER == 1, "the 512-point layout");
+        S0::template read_fn<RIN>(in[q], lane, [&](int e, int, int i) {
+          const int k2 = k0 + q;
+          return (e < NZ && !skip(k2)) ? area[q * LT::map(NZ) + mlane + (i % S0::R) * LT::map(64)]
+                                       : mk<T>(T(0), T(0));
+        });
+      } else {
+        S0::template read_fn<RIN>(in[q], lane, [&](int e, int p) {
+          const int k2 = k0 + q * PW + p;
+          return (e < NZ && !skip(k2)) ? tile[LT::at(e, k2)] : mk<T>(T(0), T(0));
+        });
+      }
+    }
     WaveSync::sync();  // the area is free once every lane holds its inputs
     cplx<T> out[Q][SL::PER][SL::R];
 #pragma unroll
@@ -880,11 +900,20 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
     }
     // the exchange reads are done: the results go back into the area
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      SL::template write_fn<ROUT>(out[q], lane, [&](int e, int p, cplx<T> v) {
-        const int k2 = k0 + q * PW + p;
-        if (e < NZ && !skip(k2)) tile[LT::at(e, k2)] = v;
-      });
+    for (int q = 0; q < Q; ++q) {
+      if constexpr (PAD == 1) {
+        static_assert(SL::NS == 64 && SL::PER == 1, "the 512-point layout");
+        SL::template write_fn<ROUT>(out[q], lane, [&](int e, int, cplx<T> v, int i) {
+          const int k2 = k0 + q;
+          if (e < NZ && !skip(k2)) area[q * LT::map(NZ) + mlane + (i % SL::R) * LT::map(64)] = v;
+        });
+      } else {
+        SL::template write_fn<ROUT>(out[q], lane, [&](int e, int p, cplx<T> v) {
+          const int k2 = k0 + q * PW + p;
+          if (e < NZ && !skip(k2)) tile[LT::at(e, k2)] = v;
+        });
+      }
+    }
     WaveSync::sync();  // this wavefront's next tuple starts from fresh reads
   }
 }
@@ -894,7 +923,7 @@ template <typename T, int M, int B, int Q, int NT>
 __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbItem<T>& it, int tid) {
   constexpr int NZ = M / Q;
   constexpr int ZPT = (NZ + NT - 1) / NT;
-  using LT = Tile<B, 1, NZ, false>;
+  using LT = Tile<B, 1, NZ, false, FbShared<T, M, B, Q>::PAD>;
   const double scale = it.br->scale;
   if (FbShared<T, M, B, Q>::kF32 && it.own0) {
     // the real k = 0 pencil input in double, from the item's pencils (still in HBM), parked as a
@@ -918,7 +947,7 @@ __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbIte
     if (NZ % NT == 0 || z < NZ) {
       cplx<T> v[B];
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) v[k2] = sh.tile[LT::at(z, k2)];
+      for (int k2 = 0; k2 < B; ++k2) v[k2] = sh.tile[LT::map(z) + k2 * LT::map(NZ)];
       if constexpr (FbShared<T, M, B, Q>::kF32) {
         if (it.own0) {
           // the k = 0 pencil in double: the padded circular convolution
@@ -951,7 +980,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_pe
   const BoxRec* br = group_box(ga, recs, t);
   const int tid = threadIdx.x;
   const FbItem<T> it = fb_item<T, M, B, Q>(br, t);
-  if constexpr (FbShared<T, M, B, Q>::kHoles) {
+  if constexpr (FbShared<T, M, B, Q>::kTwReg) {
+    // each lane reads its own twiddles from HBM in fb_pencils
+  } else if constexpr (FbShared<T, M, B, Q>::kHoles) {
     load_twiddles<T, M - 1, NT, 9, 8>(sh.tile, twm, tid);
   } else {
     load_twiddles<T, FbShared<T, M, B, Q>::kOneTw ? M : 2 * M, NT>(sh.tw, twm, tid);
@@ -960,7 +991,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_pe
   fb_dft_in<T, M, B, Q, NT>(sh, tid,
                                    [&](int jj, int z) { return it.base[(size_t)jj * (M / Q) + z]; });
   __syncthreads();
-  fb_pencils<T, M, B, Q, WV>(sh, it, tid);
+  fb_pencils<T, M, B, Q, WV>(sh, it, tid, twm);
   __syncthreads();
   fb_dft_out<T, M, B, Q, NT>(sh, it, tid);
 }
