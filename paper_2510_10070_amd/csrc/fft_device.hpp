@@ -396,13 +396,14 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
           const int pa = L::map(a);
 #pragma unroll
           for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + 3 * ((NS * L::LD) / 32))] = v[p][r];
-        } else if constexpr (L::PAD == 1 && L::LD == 1 && 32 % NS == 0 && (NS * R) % 32 == 0 &&
-                             (L::BS % 32 == 0 || L::NB == 1)) {
-          // base mod 32 = k < NS and NS divides 32: output r crosses the same 32-blocks for
-          // every k, so its offset from the padded base is a constant
+        } else if constexpr (L::PAD == 1 && 32 % (NS * L::LD) == 0 && (NS * R * L::LD) % 32 == 0 &&
+                             (L::BS % 32 == 0 || L::NB == 1 || L::NB * L::BS <= NS * L::LD)) {
+          // a mod 32 = k LD + b BS < NS LD, which divides 32: output r crosses the same 32-blocks
+          // for every lane, so its offset from the padded base is a constant
+          constexpr int C = NS * L::LD;
           const int pa = L::map(a);
 #pragma unroll
-          for (int r = 0; r < R; ++r) buf[pa + r * NS + 3 * ((r * NS) >> 5)] = v[p][r];
+          for (int r = 0; r < R; ++r) buf[pa + r * C + 3 * ((r * C) >> 5)] = v[p][r];
         } else if constexpr (NS == 1 && R == 8 && L::LD == 1 && (L::BS % 8 == 0 || L::NB == 1)) {
           // base = 8j: a multiple of 8, so the eight outputs share one pad shift (both paddings)
           const int pa = L::map(a);

@@ -43,11 +43,13 @@ template <int A, int CAP> constexpr int fa_pg() {
 
 // LDS of a pass-A (C = false) or pass-C (C = true) block for tile variant V (0..2)
 template <typename T, int NY, int A, int V, bool C> struct AcShape {
+  // float tiles pad three slots per 32 (fewer bank conflicts in the y exchanges), double pad8
+  static constexpr int PAD = sizeof(T) == 4 ? 1 : 0;
   static constexpr int NB = fa_zc<T, V>() / 2;
   static constexpr int NT = fa_threads<V>();
   // pass C with 32-byte rows and Ny <= 256: eight planes at a time, one wavefront per plane
   static constexpr int PG = C ? fa_pg<A, (V == 0 && NY <= 256) ? 8 : 4>() : fa_pg<A, 4>();
-  static constexpr int TILE = PG * lds_slots(NY * NB);  // PG plane tiles
+  static constexpr int TILE = PG * pad_slots<PAD>(NY * NB);  // PG plane tiles
 };
 // the largest tile over A in {1, 2, 4, 6, 8} (launch groups that mix Nx)
 template <typename T, int NY, int V, bool C> constexpr int ac_mix_tile() {
@@ -98,8 +100,9 @@ __device__ __forceinline__ void fa_body(const BoxRec* br, int t, const cplx<T>* 
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;        // output positions (ky, c) of one plane
   constexpr int POS = (QN + NT - 1) / NT;
-  constexpr int SLOTS = lds_slots(NY * NB);
-  using L = Tile<NB, NB, 1, true>;
+  constexpr int PAD = AcShape<T, NY, A, V, false>::PAD;
+  constexpr int SLOTS = pad_slots<PAD>(NY * NB);
+  using L = Tile<NB, NB, 1, true, PAD>;
 
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
@@ -276,8 +279,9 @@ __device__ __forceinline__ void fc_body(const BoxRec* br, int t, const cplx<T>* 
   constexpr int HY = NY / 2;
   constexpr int QN = HY * NB;
   constexpr int POS = (QN + NT - 1) / NT;
-  constexpr int SLOTS = lds_slots(NY * NB);
-  using L = Tile<NB, NB, 1, true>;
+  constexpr int PAD = AcShape<T, NY, A, V, true>::PAD;
+  constexpr int SLOTS = pad_slots<PAD>(NY * NB);
+  using L = Tile<NB, NB, 1, true, PAD>;
 
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
