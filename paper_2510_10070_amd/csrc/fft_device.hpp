@@ -54,11 +54,16 @@ template <int D, typename T> __device__ __forceinline__ cplx<T> rot(cplx<T> a) {
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
 // LDS slots needed for a tile of n logical elements
 __host__ __device__ constexpr int lds_slots(int n) { return pad8(n - 1) + 1; }
-// Second padding (PAD = 1): three spare slots after every 32 logical elements.  For the 512-point
-// 8.8.8 exchange (stride-8 writes, stride-1 reads, 64-blocked stride-8 writes) it leaves a third of
-// pad8's LDS bank conflicts.
-__host__ __device__ constexpr int pad32x3(int i) { return i + 3 * (i >> 5); }
-template <int PAD> __host__ __device__ constexpr int pad_map(int i) { return PAD == 0 ? pad8(i) : pad32x3(i); }
+// Paddings with E spare slots after every P logical elements: PAD 0 = pad8, PAD 1 = three per 32
+// (with 8-byte elements it leaves a third of pad8's LDS bank conflicts in the 8.8.8 exchanges:
+// stride-8 writes, stride-1 reads, 64-blocked stride-8 writes, and in 256-point four-column
+// transforms).
+template <int PAD> constexpr int kPadShift = PAD == 0 ? 3 : 5;
+template <int PAD> constexpr int kPadPeriod = 1 << kPadShift<PAD>;
+template <int PAD> constexpr int kPadSpare = PAD == 1 ? 3 : 1;
+template <int PAD> __host__ __device__ constexpr int pad_map(int i) {
+  return i + kPadSpare<PAD> * (i >> kPadShift<PAD>);
+}
 template <int PAD> __host__ __device__ constexpr int pad_slots(int n) { return pad_map<PAD>(n - 1) + 1; }
 // pad8(a + C) from pa = pad8(a): exact shift when C is a multiple of 8
 template <int C> __device__ __forceinline__ int pad_add(int pa, int a) {
@@ -328,10 +333,9 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
   }
   // stride-C offset r*C from the padded base
   template <int C> static __device__ __forceinline__ int pad_off(int pa, int a, int r) {
-    if constexpr (L::PAD == 0 && C % 8 == 0)
-      return pa + r * (C + C / 8);
-    else if constexpr (L::PAD == 1 && C % 32 == 0)
-      return pa + r * (C + 3 * (C / 32));
+    constexpr int P = kPadPeriod<L::PAD>, E = kPadSpare<L::PAD>;
+    if constexpr (C % P == 0)
+      return pa + r * (C + E * (C / P));
     else
       return L::map(a + r * C);
   }
@@ -392,18 +396,20 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
           const int pa = pad8(a);
 #pragma unroll
           for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + (NS * L::LD) / 8)] = v[p][r];
-        } else if constexpr (L::PAD == 1 && (NS * L::LD) % 32 == 0) {
+        } else if constexpr (L::PAD != 0 && (NS * L::LD) % kPadPeriod<L::PAD> == 0) {
+          constexpr int P = kPadPeriod<L::PAD>, E = kPadSpare<L::PAD>;
           const int pa = L::map(a);
 #pragma unroll
-          for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + 3 * ((NS * L::LD) / 32))] = v[p][r];
-        } else if constexpr (L::PAD == 1 && 32 % (NS * L::LD) == 0 && (NS * R * L::LD) % 32 == 0 &&
-                             (L::BS % 32 == 0 || L::NB == 1 || L::NB * L::BS <= NS * L::LD)) {
-          // a mod 32 = k LD + b BS < NS LD, which divides 32: output r crosses the same 32-blocks
-          // for every lane, so its offset from the padded base is a constant
-          constexpr int C = NS * L::LD;
+          for (int r = 0; r < R; ++r) buf[pa + r * (NS * L::LD + E * ((NS * L::LD) / P))] = v[p][r];
+        } else if constexpr (L::PAD != 0 && kPadPeriod<L::PAD> % (NS * L::LD) == 0 &&
+                             (NS * R * L::LD) % kPadPeriod<L::PAD> == 0 &&
+                             (L::BS % kPadPeriod<L::PAD> == 0 || L::NB == 1 || L::NB * L::BS <= NS * L::LD)) {
+          // a mod P = k LD + b BS < NS LD, which divides P: output r crosses the same periods for
+          // every lane, so its offset from the padded base is a constant
+          constexpr int P = kPadPeriod<L::PAD>, E = kPadSpare<L::PAD>, C = NS * L::LD;
           const int pa = L::map(a);
 #pragma unroll
-          for (int r = 0; r < R; ++r) buf[pa + r * C + 3 * ((r * C) >> 5)] = v[p][r];
+          for (int r = 0; r < R; ++r) buf[pa + r * C + E * ((r * C) / P)] = v[p][r];
         } else if constexpr (NS == 1 && R == 8 && L::LD == 1 && (L::BS % 8 == 0 || L::NB == 1)) {
           // base = 8j: a multiple of 8, so the eight outputs share one pad shift (both paddings)
           const int pa = L::map(a);

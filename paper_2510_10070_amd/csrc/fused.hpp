@@ -713,8 +713,10 @@ template <typename T, int M, int B, int Q> struct FbShared {
   // register twiddles (read once from HBM): the tile needs no twiddle slots, and at M = 512 it
   // takes the padding with fewer bank conflicts in the 8.8.8 exchanges
   static constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
+  // the float 8.8.8 one-pencil exchange: three spare slots per 32 (double tiles keep pad8, whose
+  // spare slots hold the twiddle table; one spare slot per 16 measured slower there)
   static constexpr int PAD = (kTwReg && PW == 1 && M == 512) ? 1 : 0;
-  static constexpr bool kHoles = !kTwReg && fb_tw_in_holes<M, B, Q>();
+  static constexpr bool kHoles = !kTwReg && PAD == 0 && fb_tw_in_holes<M, B, Q>();
   cplx<T> tile[pad_slots<PAD>(B * NZ)];
   cplx<T> tw[(kHoles || kTwReg) ? 1 : kOneTw ? M : 2 * M];
   T pa0[B], pe[B], pik[B], pk2[B], psp[B];  // Green's-function coefficients of the B modes
@@ -865,7 +867,7 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
     cplx<T> in[Q][S0::PER][S0::R];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      if constexpr (PAD == 1) {
+      if constexpr (PAD != 0) {
         // one pencil per transform and e = lane + 64 r: slot map(lane) + r map(64) in its pencil
         static_assert(PW == 1 && S0::NBF == 64 && S0::PER == 1, "the 512-point layout");
         S0::template read_fn<RIN>(in[q], lane, [&](int e, int, int i) {
@@ -905,7 +907,7 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
     // the exchange reads are done: the results go back into the area
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      if constexpr (PAD == 1) {
+      if constexpr (PAD != 0) {
         static_assert(SL::NS == 64 && SL::PER == 1, "the 512-point layout");
         SL::template write_fn<ROUT>(out[q], lane, [&](int e, int, cplx<T> v, int i) {
           const int k2 = k0 + q;
