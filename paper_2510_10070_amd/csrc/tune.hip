@@ -26,6 +26,9 @@ void default_variants(int prec, const BoxGeom& g, int var[kKinds]) {
   // with A = Nx/16 <= 8 planes a thread holds half the spectra of A = 16 or less, which leaves room
   // for 64-byte rows (variant 1): twice the z cells per block, half the blocks
   if (prec && g.nx <= 128 && g.ny <= 256) var[kFA] = var[kFC] = 1;
+  // five-pass float y transforms longer than 512: half-width rows (1024 x 1024 x 256: 809 -> 552 us
+  // forward, 1235 -> 696 us inverse, the autotuner's choice too)
+  if (prec && g.ny > 512) var[kYFwd] = var[kYInv] = 0;
 }
 
 namespace {
