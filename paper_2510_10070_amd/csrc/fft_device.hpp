@@ -2,9 +2,9 @@
 // register-resident Stockham auto-sort schedule whose stages exchange data through LDS.
 //
 // A tile holds NB independent length-N transforms; element j of transform b has the logical
-// index j*LD + b*BS and the LDS slot pad8(logical) = i + i/8 (one spare slot every eight
-// elements breaks the power-of-two strides of the Stockham write pattern, which would
-// otherwise land on the same LDS banks).
+// index j*LD + b*BS and, by default, the LDS slot pad8(logical) = i + i/8 (one spare slot every
+// eight elements breaks the power-of-two strides of the Stockham write pattern, which would
+// otherwise land on the same LDS banks); a tile may choose three spare slots per 32 instead.
 //
 // Stage s of radix R (Ns = product of the earlier radices) takes, for butterfly j of
 // transform b, the R inputs j + r N/R, applies the twiddles exp(-+2 pi i k r/(Ns R)),
@@ -65,13 +65,6 @@ template <int PAD> __host__ __device__ constexpr int pad_map(int i) {
   return i + kPadSpare<PAD> * (i >> kPadShift<PAD>);
 }
 template <int PAD> __host__ __device__ constexpr int pad_slots(int n) { return pad_map<PAD>(n - 1) + 1; }
-// pad8(a + C) from pa = pad8(a): exact shift when C is a multiple of 8
-template <int C> __device__ __forceinline__ int pad_add(int pa, int a) {
-  if constexpr (C % 8 == 0)
-    return pa + C + C / 8;
-  else
-    return pad8(a + C);
-}
 
 // ------------------------------------------------------------------------------------------
 // Radix-R DFTs in registers.  D = -1: X_k = sum x_n exp(-2 pi i nk/R); D = +1: conjugate kernel.
