@@ -41,7 +41,7 @@ template <int A, int CAP> constexpr int fa_pg() {
   return p;
 }
 
-// LDS of a pass-A (C = false) or pass-C (C = true) block for tile variant V (0..2)
+// LDS of a pass-A (C = false) or pass-C (C = true) block for tile variant V in {0, 1, 2}
 template <typename T, int NY, int A, int V, bool C> struct AcShape {
   // float tiles pad three slots per 32 (fewer bank conflicts in the y exchanges), double pad8
   static constexpr int PAD = sizeof(T) == 4 ? 1 : 0;
@@ -687,13 +687,15 @@ template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves
 
 // Twiddles: the stage-major table of the forward schedule of M, then that of the inverse one if
 // it differs.  When one table serves both and the tile's spare pad8 slots can hold it, it lives
-// there (TwH), which keeps pass B's LDS small enough for four blocks per CU in float.
+// there (TwH), which keeps pass B's LDS small enough for four blocks per CU in float (M = 512 in
+// float needs neither: its twiddles live in registers, below).
 template <int M, int B, int Q> constexpr bool fb_tw_in_holes() {
   return same_schedule<typename Fwd<M>::L, typename Inv<M>::L>() && B * (M / Q) >= 8 * (M - 1) + 8;
 }
-// Float plans whose schedule gives each lane one butterfly per stage (M = 512) keep the lane's
-// twiddles in registers instead (pass B is bound by LDS issue, and those reads are the same for
-// every pencil): the extra registers cost one block per CU, which measured as the better trade.
+// Float plans whose schedule gives each lane one butterfly per stage keep the lane's twiddles in
+// registers, read once per block from the table in HBM: pass B is bound by LDS issue, and those
+// reads would be the same for every pencil.  The hint asks for at least three waves per SIMD
+// (the M = 512 kernel fits four).
 template <typename T, int M, int B, int Q> constexpr bool fb_tw_in_registers() {
   using S0 = Stage<T, M, typename Fwd<M>::L, 0, Tile<fb_pw<M, B, Q>(), 1, M, false>, 64, -1>;
   return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && S0::PER == 1;
@@ -842,7 +844,7 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
   const bool own0 = it.own0;
   const int wave = tid >> 6, lane = tid & 63;
   cplx<T>* tile = sh.tile;
-  // the lane's twiddles, the same for every pencil, read from LDS once when registers allow (the
+  // the lane's twiddles, the same for every pencil, read once from HBM when registers allow (the
   // inverse schedule equals the forward one wherever this applies: fb_tw_in_holes)
   constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
   TwReg<T, M, RF, LW, 64, TwS<T>> twr{TwS<T>{twm}};  // from the stage-major table in HBM
