@@ -167,8 +167,9 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   constexpr int ZC = y_zc<T, NY, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = kPassThreads;
-  using L = Tile<NB, NB, 1, true>;
-  __shared__ cplx<T> tile[lds_slots(NY * NB)];
+  constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
+  using L = Tile<NB, NB, 1, true, PAD>;
+  __shared__ cplx<T> tile[pad_slots<PAD>(NY * NB)];
   __shared__ cplx<T> tw[NY];
   __shared__ cplx<T> ph[NY / 2];
   __shared__ double red[2][NT / 64];
@@ -275,8 +276,9 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   constexpr int ZC = y_zc<T, NY, V>();
   constexpr int NB = ZC / 2;
   constexpr int NT = kPassThreads;
-  using L = Tile<NB, NB, 1, true>;
-  __shared__ cplx<T> tile[lds_slots(NY * NB)];
+  constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
+  using L = Tile<NB, NB, 1, true, PAD>;
+  __shared__ cplx<T> tile[pad_slots<PAD>(NY * NB)];
   __shared__ cplx<T> tw[NY];
   __shared__ cplx<T> ph[NY / 2];
 
@@ -378,8 +380,9 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
                                                     const cplx<T>* __restrict__ twg) {
   constexpr int ZC = x_zc<T, NX, V>();
   constexpr int NT = kPassThreads;
-  using L = Tile<ZC, ZC, 1, true>;
-  __shared__ cplx<T> buf[lds_slots(NX * ZC)];
+  constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
+  using L = Tile<ZC, ZC, 1, true, PAD>;
+  __shared__ cplx<T> buf[pad_slots<PAD>(NX * ZC)];
   __shared__ cplx<T> tw[NX];
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -427,8 +430,10 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   constexpr int WV = kPassThreads / 64;
   constexpr int NT = kPassThreads;
   constexpr bool kF32 = std::is_same<T, float>::value;
-  using LW = Tile<PW, 1, M, false>;
-  constexpr int XS = lds_slots(PW * M);
+  // float 512-point pencils, one per transform: three spare slots per 32 (bank conflicts)
+  constexpr int PAD = (kF32 && PW == 1 && M == 512) ? 1 : 0;
+  using LW = Tile<PW, 1, M, false, PAD>;
+  constexpr int XS = pad_slots<PAD>(PW * M);
   __shared__ cplx<T> xbuf[WV * XS];
   // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
   constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
