@@ -388,10 +388,10 @@ __device__ __forceinline__ void fc_body(const BoxRec* br, int t, const cplx<T>* 
       // cells, so the transformed columns stay in LDS for the interpolation
       YInterp yi;
       yi.init(br->shy * (x + 0.5), NY);
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true>(
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true, 0, 1, Sy>(
           mytile, TwS<T>{tw}, stid, [&](int e, int c) { return mytile[L::at(e, c)]; },
           [&](int e, int c, cplx<T> v) { mytile[L::at(e, c)] = v; });
-      __syncthreads();
+      Sy::sync();  // the interpolation reads this wavefront's own plane only when TNT = 64
       for (int w = stid; w < NY * NB; w += TNT) {
         const int c = w % NB, e = w / NB;
         store(e, c, yi.sample<T>(e, NY, [&](int y) { return mytile[L::at(y, c)]; }));
@@ -450,6 +450,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __
   static_assert(2 * QN <= NT, "one position per lane pair");
   constexpr int PG = fa_pg<A, 8>();
   constexpr int TNT = NT / PG;
+  // a transform owned by one wavefront needs no workgroup barrier between its stages
+  using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
   constexpr int SLOTS = lds_slots(NY * NB);
   using L = Tile<NB, NB, 1, true>;
   __shared__ cplx<T> tile[PG * SLOTS];
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __
     gmem<const T>* src = rho + (size_t)x * NY * nz + z0;
     YInterp yi;
     if (LIN) yi.init(-br->shy * (x + 0.5), NY);
-    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true>(
+    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(
         mytile, TwS<T>{tw}, stid,
         [&](int e, int cc) {
           cplx<T> v = mk<T>(T(0), T(0));
@@ -565,6 +567,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fcs(GroupArgs ga, const BoxRec* __
   static_assert(2 * QN <= NT, "one position per lane pair");
   constexpr int PG = fa_pg<A, 8>();
   constexpr int TNT = NT / PG;
+  // a transform owned by one wavefront needs no workgroup barrier between its stages
+  using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
   constexpr int SLOTS = lds_slots(NY * NB);
   using L = Tile<NB, NB, 1, true>;
   __shared__ cplx<T> tile[PG * SLOTS];
@@ -648,16 +652,16 @@ __global__ __launch_bounds__(kFusedAC) void k_fcs(GroupArgs ga, const BoxRec* __
     if constexpr (LIN) {
       YInterp yi;
       yi.init(br->shy * (x + 0.5), NY);
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true>(
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true, 0, 1, Sy>(
           mytile, TwS<T>{tw}, stid, [&](int e, int cc) { return mytile[L::at(e, cc)]; },
           [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; });
-      __syncthreads();
+      Sy::sync();
       for (int w = stid; w < NY * NB; w += TNT) {
         const int cc = w % NB, e = w / NB;
         store(e, cc, yi.sample<T>(e, NY, [&](int y) { return mytile[L::at(y, cc)]; }));
       }
     } else {
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false>(
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false, 0, 1, Sy>(
           mytile, TwS<T>{tw}, stid, [&](int e, int cc) { return mytile[L::at(e, cc)]; }, store);
     }
     __syncthreads();  // the tiles are rebuilt for the next planes
