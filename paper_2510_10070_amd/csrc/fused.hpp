@@ -48,7 +48,7 @@ template <typename T, int NY, int A, int V, bool C> struct AcShape {
   static constexpr int NB = fa_zc<T, V>() / 2;
   static constexpr int NT = fa_threads<V>();
   // pass C with 32-byte rows and Ny <= 256: eight planes at a time, one wavefront per plane
-  static constexpr int PG = C ? fa_pg<A, (V == 0 && NY <= 256) ? 8 : 4>() : fa_pg<A, V == 1 ? 8 : 4>();
+  static constexpr int PG = C ? fa_pg<A, ((V == 0 || V == 1) && NY <= 256) ? 8 : 4>() : fa_pg<A, V == 1 ? 8 : 4>();
   static constexpr int TILE = PG * pad_slots<PAD>(NY * NB);  // PG plane tiles
 };
 // the largest tile over A in {1, 2, 4, 6, 8} (launch groups that mix Nx)
