@@ -964,15 +964,22 @@ __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbIte
         if (it.own0) {
           // the k = 0 pencil in double: the padded circular convolution
           // phi_0[z] = scale sum_z' h[(z - z') mod M] d0[z']
+          // four partial sums over zp = 4i + u, so that each round has four independent loads of
+          // h in flight (rounds are not unrolled: more loads in flight would raise the register
+          // allocation of the whole kernel)
           gmem<const double>* h = hbm(it.br->k0h);
-          double acc = 0.0;
-#pragma unroll 2
-          for (int zp = 0; zp < NZ; ++zp) {
-            const int d = z - zp;
-            const cplx<T> d0 = sh.tile[LT::at(zp, 0)];
-            acc += h[d < 0 ? d + M : d] * ((double)d0.x + (double)d0.y);
+          static_assert(NZ % 4 == 0, "z cells in groups of four");
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+          for (int zp = 0; zp < NZ; zp += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int d = z - zp - u;
+              const cplx<T> d0 = sh.tile[LT::at(zp + u, 0)];
+              acc[u] += h[d < 0 ? d + M : d] * ((double)d0.x + (double)d0.y);
+            }
           }
-          v[0] = mk<T>((T)(acc * scale), T(0));
+          v[0] = mk<T>((T)(((acc[0] + acc[1]) + (acc[2] + acc[3])) * scale), T(0));
         }
       }
       Dft<B, +1, T>::run(v);

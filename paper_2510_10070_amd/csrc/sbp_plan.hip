@@ -385,11 +385,18 @@ void build_launches(sbp_plan p) {
       }
       l.blocks = acc;
       if (l.n > 1) {
-        // (box id, tile) of every block, so that a block finds its box with one load
+        // (box id, tile) of every block, so that a block finds its box with one load.  Pass B
+        // lists tile 0 of every box first: in float that block also convolves the k = 0 pencil
+        // in double, the longest block of the launch, so it should not start last.
         l.blk_off = p->blk.size() / 2;
+        const int first = kind == sbp::kFB ? 1 : 0;
+        for (int i = 0; i < l.n && first; ++i) {
+          p->blk.push_back(kv.second[i]);
+          p->blk.push_back(0);
+        }
         for (int i = 0; i < l.n; ++i) {
           const int nt = p->ints[l.ints_off + l.n + i + 1] - p->ints[l.ints_off + l.n + i];
-          for (int t = 0; t < nt; ++t) {
+          for (int t = first; t < nt; ++t) {
             p->blk.push_back(kv.second[i]);
             p->blk.push_back(t);
           }
