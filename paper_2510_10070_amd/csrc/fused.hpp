@@ -952,6 +952,50 @@ __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbIte
       }
     }
     __syncthreads();
+    // every thread takes its pencil values into registers; then the slots after pencil 0 hold
+    // the convolution kernel h (M doubles), so that the convolution reads it from LDS
+    cplx<T> vk[ZPT][B];
+#pragma unroll
+    for (int zi = 0; zi < ZPT; ++zi) {
+      const int z = tid + zi * NT;
+      if (NZ % NT == 0 || z < NZ) {
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) vk[zi][k2] = sh.tile[LT::map(z) + k2 * LT::map(NZ)];
+      }
+    }
+    static_assert(pad_map<LT::PAD>(NZ) + M <= pad_slots<LT::PAD>(B * NZ), "h fits after pencil 0");
+    double* hl = reinterpret_cast<double*>(sh.tile + LT::map(NZ));
+    __syncthreads();  // every pencil value has been read
+    {
+      gmem<const double>* h = hbm(it.br->k0h);
+      for (int i = tid; i < M; i += NT) hl[i] = h[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int zi = 0; zi < ZPT; ++zi) {
+      const int z = tid + zi * NT;
+      if (NZ % NT == 0 || z < NZ) {
+        // the k = 0 pencil in double: the padded circular convolution
+        // phi_0[z] = scale sum_z' h[(z - z') mod M] d0[z'], four partial sums over z' = 4i + u
+        static_assert(NZ % 4 == 0, "z cells in groups of four");
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int zp = 0; zp < NZ; zp += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int d = z - zp - u;
+            const cplx<T> d0 = sh.tile[LT::at(zp + u, 0)];
+            acc[u] += hl[d < 0 ? d + M : d] * ((double)d0.x + (double)d0.y);
+          }
+        }
+        auto& v = vk[zi];
+        v[0] = mk<T>((T)(((acc[0] + acc[1]) + (acc[2] + acc[3])) * scale), T(0));
+        Dft<B, +1, T>::run(v);
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj) it.base[(size_t)jj * NZ + z] = v[jj];
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int zi = 0; zi < ZPT; ++zi) {
@@ -960,28 +1004,6 @@ __device__ __forceinline__ void fb_dft_out(FbShared<T, M, B, Q>& sh, const FbIte
       cplx<T> v[B];
 #pragma unroll
       for (int k2 = 0; k2 < B; ++k2) v[k2] = sh.tile[LT::map(z) + k2 * LT::map(NZ)];
-      if constexpr (FbShared<T, M, B, Q>::kF32) {
-        if (it.own0) {
-          // the k = 0 pencil in double: the padded circular convolution
-          // phi_0[z] = scale sum_z' h[(z - z') mod M] d0[z']
-          // four partial sums over zp = 4i + u, so that each round has four independent loads of
-          // h in flight (rounds are not unrolled: more loads in flight would raise the register
-          // allocation of the whole kernel)
-          gmem<const double>* h = hbm(it.br->k0h);
-          static_assert(NZ % 4 == 0, "z cells in groups of four");
-          double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-          for (int zp = 0; zp < NZ; zp += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int d = z - zp - u;
-              const cplx<T> d0 = sh.tile[LT::at(zp + u, 0)];
-              acc[u] += h[d < 0 ? d + M : d] * ((double)d0.x + (double)d0.y);
-            }
-          }
-          v[0] = mk<T>((T)(((acc[0] + acc[1]) + (acc[2] + acc[3])) * scale), T(0));
-        }
-      }
       Dft<B, +1, T>::run(v);
 #pragma unroll
       for (int jj = 0; jj < B; ++jj) it.base[(size_t)jj * NZ + z] = v[jj];
