@@ -153,8 +153,9 @@ sbp_status sbp_ghosts(sbp_plan plan, const void* const* phi, void* const* out, i
 sbp_status sbp_gravity(sbp_plan plan, const void* const* phi, void* const* gx, void* const* gy, void* const* gz,
                        const sbp_shear* params, void* stream);
 
-/* Free the plan and everything it allocated.  Call only after the stream used by its
- * solves has been synchronised.  NULL is accepted and ignored. */
+/* Free the plan and everything it allocated.  It first waits for all work on the plan's device
+ * (hipDeviceSynchronize), so that nothing still queued reads what it frees; it must therefore
+ * not be called while a stream of that device is being captured.  NULL is accepted and ignored. */
 sbp_status sbp_plan_destroy(sbp_plan plan);
 
 /* Static description of a status code. */

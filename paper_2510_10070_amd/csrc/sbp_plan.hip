@@ -103,6 +103,7 @@ struct sbp_plan_s {
   std::vector<std::string> names;  // stable storage for sbp_profile_read
   std::string describe;
   std::string tune_source = "defaults";
+  bool nomix = false;  // autotuning: no merged mixed-Nx groups
 };
 
 namespace {
@@ -349,7 +350,7 @@ void build_launches(sbp_plan p) {
       const int lin = (kind == sbp::kFA || kind == sbp::kFC) && bi.g.remap == SBP_REMAP_LINEAR;
       groups[std::make_tuple(kind_len(bi, kind), bi.var[kind], q, a, lin)].push_back(b);
     }
-    if ((kind == sbp::kFA || kind == sbp::kFC) && p->prec == SBP_FP32) {
+    if ((kind == sbp::kFA || kind == sbp::kFC) && p->prec == SBP_FP32 && !p->nomix) {
       // float passes A and C in 64-byte rows (A <= 8): groups that differ only in A share one
       // launch (k_fa_mix / k_fc_mix, a = 0), rather than one small launch each
       std::map<std::tuple<int, int, int, int>, std::vector<std::tuple<int, int, int, int, int>>> same;
@@ -540,8 +541,10 @@ std::string describe_plan(sbp_plan p) {
   s += ",\"groups\":[";
   for (size_t i = 0; i < p->launches.size(); ++i) {
     const Launch& l = p->launches[i];
-    snprintf(buf, sizeof buf, "%s{\"pass\":\"%s\",\"len\":%d,\"variant\":%d,\"boxes\":%d,\"blocks\":%d}",
-             i ? "," : "", kPassName[l.kind], l.len, l.variant, l.n, l.blocks);
+    const BoxInfo& b0 = p->boxes[p->ints[l.ints_off]];
+    snprintf(buf, sizeof buf,
+             "%s{\"pass\":\"%s\",\"len\":%d,\"variant\":%d,\"tuned\":\"%s\",\"boxes\":%d,\"blocks\":%d}",
+             i ? "," : "", kPassName[l.kind], l.len, l.variant, sbp::kVarSrcName[b0.var_src[l.kind]], l.n, l.blocks);
     s += buf;
   }
   s += "]}";
@@ -577,6 +580,8 @@ int plan_prec(sbp_plan p) { return p->prec; }
 int plan_device(sbp_plan p) { return p->device; }
 std::vector<BoxInfo>& plan_boxes(sbp_plan p) { return p->boxes; }
 void plan_set_tune_source(sbp_plan p, const std::string& s) { p->tune_source = s; }
+void plan_set_nomix(sbp_plan p, bool on) { p->nomix = on; }
+int plan_group_box(sbp_plan p, const Launch& l) { return p->ints[l.ints_off]; }
 
 // Time every launch group of the current variant assignment (reps solves after one warm-up) on
 // scratch buffers.  ms[i] is the mean time of launches()[i].
@@ -1057,6 +1062,10 @@ sbp_status sbp_gravity(sbp_plan p, const void* const* phi, void* const* gx, void
 sbp_status sbp_plan_destroy(sbp_plan p) {
   if (!p) return SBP_OK;
   hipSetDevice(p->device);
+  // work enqueued by this plan may still read its tables, records, ring and workspace: wait for
+  // the device before freeing them (a plan is destroyed rarely; the streams it was used on are
+  // not tracked, and may already be gone)
+  hipDeviceSynchronize();
   destroy_graph(p);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   for (auto& r : p->pending) {

@@ -39,10 +39,20 @@ struct BoxInfo {
   int npartials = 0;
   size_t data_bytes = 0;
   int var[kKinds] = {1, 1, 1, 1, 1, 0, 0, 0};  // tile variant per pass kind
+  int var_src[kKinds] = {0, 0, 0, 0, 0, 0, 0, 0};  // where var[k] came from: kVarSrc*
   bool fused = false;                           // three-pass schedule for this box
 };
 
 sbp_status fail(sbp_status st, const char* fmt, ...);
+
+// origin of a box's tile variant for one pass kind
+enum VarSrc { kVarDefault = 0, kVarCache = 1, kVarMeasured = 2 };
+extern const char* const kVarSrcName[3];
+
+// whether tile variant v exists for pass kind `kind` of a fused box (passes A and C only; the
+// launchers reject every other combination)
+bool fused_variant_ok(int prec, int kind, const BoxGeom& g, int v);
+constexpr int kFusedVariants = 4;
 
 // built-in variant choice (measured on MI355X) for a box
 void default_variants(int prec, const BoxGeom& g, int var[kKinds]);
@@ -54,6 +64,11 @@ int plan_prec(sbp_plan p);
 int plan_device(sbp_plan p);
 std::vector<BoxInfo>& plan_boxes(sbp_plan p);
 void plan_set_tune_source(sbp_plan p, const std::string& s);
+// while the autotuner times the fused passes, every (Ny, A) keeps its own launch group (float
+// plans otherwise merge groups that differ only in A <= 8 into one launch)
+void plan_set_nomix(sbp_plan p, bool on);
+// index of the first box of a launch group
+int plan_group_box(sbp_plan p, const Launch& l);
 sbp_status plan_time_groups(sbp_plan p, int reps, std::vector<Launch>& launches, std::vector<double>& ms);
 
 }  // namespace sbp

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2510_10070_amd.inputs import gaussian_noise_density, lognormal_density
 
-from .gpu_util import gpu_solve, oracle_solve, rel_l2
+from .gpu_util import condition_tolerance, gpu_solve, max_pointwise_error, oracle_solve, per_mode_error, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +41,11 @@ def test_parity_noise(shape, method, precision):
     got, used = gpu_solve(box, rho, shear, precision)
     ref = oracle_solve(box, used[0], shear)
     err = rel_l2(got[0], ref)
-    print(f"{shape} {method} {precision}: rel-L2 {err:.3e}")
+    pm, mp = per_mode_error(got[0], ref), max_pointwise_error(got[0], ref)
+    print(f"{shape} {method} {precision}: rel-L2 {err:.3e}, per-mode {pm:.3e}, max pointwise {mp:.3e}")
     assert err <= TOL[precision], err
+    assert pm <= TOL[precision], pm
+    assert mp <= TOL[precision], mp
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -244,6 +247,11 @@ FUSED_SHAPES = [
     (96, 96, 96, 1.0, 1.5, 1.0, 2, 0.0),  # A = 6, Ny = 96, M = 192
     (96, 16, 32, 1.0, 1.0, 1.0, 2, 0.0),
     (32, 32, 8, 1.0, 1.0, 0.5, 4, 0.0),  # fewer z cells than one 64-byte row: a ragged tile
+    # 4x padding in pass B: M = 128, 192, 256, 512 (tile layouts and k = 0 staging of Q = 4)
+    (16, 16, 32, 1.0, 1.0, 1.0, 4, 0.0),
+    (32, 16, 48, 1.0, 1.0, 1.0, 4, 1.3),
+    (16, 32, 64, 1.0, 1.0, 1.0, 4, 0.0),
+    (16, 16, 128, 1.0, 1.0, 1.0, 4, 0.0),
 ]
 
 
@@ -259,9 +267,15 @@ def test_fused_schedule_parity(shape, method, precision):
     err = rel_l2(got[0], ref)
     five, _ = gpu_solve(box, used[0], shear, precision, schedule="five_pass")
     err5 = rel_l2(five[0], ref)
-    print(f"{shape} {method} {precision}: fused {err:.3e} five-pass {err5:.3e}")
+    pm, pm5 = per_mode_error(got[0], ref), per_mode_error(five[0], ref)
+    print(f"{shape} {method} {precision}: fused {err:.3e} (per-mode {pm:.3e}) five-pass {err5:.3e} "
+          f"(per-mode {pm5:.3e})")
     assert err <= TOL[precision], err
     assert err5 <= TOL[precision], err5
+    assert pm <= TOL[precision], pm
+    assert pm5 <= TOL[precision], pm5
+    assert max_pointwise_error(got[0], ref) <= TOL[precision]
+    assert max_pointwise_error(five[0], ref) <= TOL[precision]
 
 
 def test_fused_is_selected_and_mixed_schedules():
@@ -306,3 +320,138 @@ def test_linear_remap_parity(case, method, precision, schedule):
     err = rel_l2(got[0], oracle_solve(box, used[0], shear))
     print(f"{shape} linear {method} {precision} {schedule}: rel-L2 {err:.3e}")
     assert err <= TOL[precision], err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_ring_wraps_with_changing_shear(precision):
+    # a graph plan reads each solve's records from a pinned ring of 64 slots through a device-side
+    # counter that the replayed fetch kernel advances.  70 replays without synchronisation wrap the
+    # ring; the shear time changes every replay and the outputs alternate, so the last two replays
+    # (different records, different slots) are both checked against the oracle.
+    import torch
+
+    from paper_2510_10070_amd import Box, Plan, Shear
+
+    shape = (32, 16, 16)
+    box = _box(shape + (1.0, 1.0, 1.0, 2, 0.0), "sasha")
+    rho = lognormal_density(shape, 1.0, 0.2, seed=301)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    r = torch.tensor(rho, dtype=dt, device="cuda:0")
+    outs = [torch.empty_like(r) for _ in range(2)]
+    plan = Plan(Box(**box), precision=precision, graph=True)
+    shear = lambda k: (1.5, 1.0, 0.013 * k, 1.0 + 0.002 * k)
+    nsolve = 70
+    for k in range(nsolve):
+        plan.solve(r, outs[k % 2], Shear(*shear(k)))
+    torch.cuda.synchronize()
+    used = r.double().cpu().numpy()
+    for k in (nsolve - 2, nsolve - 1):
+        err = rel_l2(outs[k % 2].double().cpu().numpy(), oracle_solve(box, used, shear(k)))
+        assert err <= TOL[precision], (k, err)
+    # and again, past a second wrap, after synchronising in between
+    for k in range(nsolve, 2 * nsolve):
+        plan.solve(r, outs[k % 2], Shear(*shear(k)))
+    torch.cuda.synchronize()
+    k = 2 * nsolve - 1
+    assert rel_l2(outs[k % 2].double().cpu().numpy(), oracle_solve(box, used, shear(k))) <= TOL[precision]
+    plan.close()
+
+
+@pytest.mark.parametrize("schedule", ["fused", "five_pass", "plain"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sasha_zero_total_mass(schedule, precision):
+    # SASHA takes z0 = sum(z rho)/sum(rho); with sum(rho) = 0 the analytic part is dropped
+    # (Phi_0 = 0).  rho = 0 must give Phi = 0 exactly; a zero-mean density must match the oracle,
+    # which takes the same branch.
+    if schedule == "plain" and precision == "fp32":
+        pytest.skip("the plain path is FP64 only")
+    shape = (32, 16, 16)
+    box = _box(shape + (1.0, 1.0, 1.0, 2, 0.0), "sasha")
+    kw = dict(plain=True) if schedule == "plain" else dict(schedule=schedule)
+    shear = (1.5, 1.0, 0.4, 1.0)
+    zero = np.zeros(shape)
+    got, _ = gpu_solve(box, zero, shear, precision, **kw)
+    assert np.all(got[0] == 0.0)
+    # a zero-mean density of small integers: every partial sum is exact in any order and
+    # precision, so both sides see sum(rho) = 0 exactly
+    sign = np.where(np.arange(32) % 2 == 0, 1.0, -1.0)[:, None, None]
+    rho = sign * (1.0 + (np.arange(16) % 3)[None, :, None] + (np.arange(16) % 2)[None, None, :])
+    assert rho.sum() == 0.0
+    got, used = gpu_solve(box, rho, shear, precision, **kw)
+    ref = oracle_solve(box, used[0], shear)
+    assert rel_l2(got[0], ref) <= TOL[precision]
+
+
+# FP32 checks that an error confined to a few high-|k| modes cannot hide under rel-L2: per-mode
+# comparison on a random field, and densities that excite only the top horizontal modes
+@pytest.mark.parametrize("schedule", ["fused", "five_pass"])
+def test_fp32_per_mode_and_pointwise(schedule):
+    from paper_2510_10070_amd.inputs import grf_density
+
+    shape = (64, 64, 32)
+    box = _box(shape + (2.0, 2.0, 3.0, 2, 0.0), "vgf")
+    rho = grf_density(shape, (2.0, 2.0, 3.0), 0.5, seed=401)
+    shear = (1.5, 1.0, 0.3, 1.0)
+    got, used = gpu_solve(box, rho, shear, "fp32", schedule=schedule)
+    ref = oracle_solve(box, used[0], shear)
+    pm, mp = per_mode_error(got[0], ref), max_pointwise_error(got[0], ref)
+    print(f"grf 64x64x32 fp32 {schedule}: per-mode {pm:.3e}, max pointwise {mp:.3e}, rel-L2 {rel_l2(got[0], ref):.3e}")
+    assert pm <= TOL["fp32"], pm
+    assert mp <= TOL["fp32"], mp
+
+
+def _top_mode_wave(shape, lengths, s, mx, my):
+    """cos(Kx x) cos(Ky (y + s x)) exp(-z^2/2 H^2) at mode numbers (mx, my): shear-periodic."""
+    nx, ny, nz = shape
+    lx, ly, lz = lengths
+    x = (np.arange(nx) + 0.5) * lx / nx
+    y = (np.arange(ny) + 0.5) * ly / ny
+    z = -0.5 * lz + (np.arange(nz) + 0.5) * lz / nz
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    h = np.cos(2 * np.pi * mx * X / lx) * np.cos(2 * np.pi * my * (Y + s * X) / ly)
+    return h[:, :, None] * np.exp(-0.5 * (z / (0.2 * lz)) ** 2)[None, None, :]
+
+
+@pytest.mark.parametrize("schedule", ["fused", "five_pass"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("shape", [(64, 64, 32), (256, 32, 16), (96, 96, 24)], ids=lambda s: "x".join(map(str, s)))
+def test_top_horizontal_modes(shape, precision, schedule):
+    # waves at the largest mode numbers in x and y (and their mix), so the whole result lives in the
+    # high-|k| pencils that a wrong twiddle, tile row or padding slot there would corrupt.  Such an
+    # input is ill-conditioned for any solve in float (rounding in the other modes is weighed by
+    # their far larger Green's function): the bound is the FP32 tolerance or 20 eps kappa, whichever
+    # is larger (condition_tolerance), at most 5e-4 here, far below the O(1) error of such a bug.
+    lengths = (1.0, 1.0, 1.0)
+    q, om, t, G = 1.5, 1.0, 0.5, 1.0  # s = 0.75
+    s = (q * om * lengths[0] * t) % lengths[1] / lengths[0]
+    nx, ny, _ = shape
+    box = _box(shape + lengths + (2, 0.0), "vgf")
+    for mx, my in ((nx // 2 - 1, 1), (1, ny // 2 - 1), (nx // 2 - 1, ny // 2 - 1), (nx // 3, ny // 2 - 2)):
+        rho = _top_mode_wave(shape, lengths, s, mx, my)
+        got, used = gpu_solve(box, rho, (q, om, t, G), precision, schedule=schedule)
+        ref = oracle_solve(box, used[0], (q, om, t, G))
+        tol = condition_tolerance(used[0], box, (q, om, t, G), precision)
+        assert tol <= (5e-4 if precision == "fp32" else 1e-11)
+        err, mp = rel_l2(got[0], ref), max_pointwise_error(got[0], ref)
+        print(f"{shape} mode ({mx},{my}) {precision} {schedule}: rel-L2 {err:.3e}, max pointwise {mp:.3e}, "
+              f"bound {tol:.2e}")
+        assert err <= tol, (mx, my, err)
+        assert mp <= 2 * tol, (mx, my, mp)
+
+
+def test_max_box_count():
+    # the largest plan the ABI accepts: 4096 boxes (tiny, of three shapes, both methods, per-box
+    # shear), one FP32 solve, each box against the oracle
+    shapes = [(8, 8, 4), (16, 8, 4), (8, 16, 8)]
+    boxes, rhos, shears = [], [], []
+    for i in range(4096):
+        s = shapes[i % 3]
+        boxes.append(_box(s + (1.0, 1.0 + 0.01 * (i % 7), 1.0, 2, 0.0), "sasha" if i % 5 == 0 else "vgf"))
+        rhos.append(lognormal_density(s, 1.0, 0.2, seed=1000 + i))
+        shears.append((1.5, 1.0, 0.001 * i, 1.0))
+    got, used = gpu_solve(boxes, rhos, shears, "fp32")
+    worst = 0.0
+    for b, g, u, s in zip(boxes, got, used, shears):
+        worst = max(worst, rel_l2(g, oracle_solve(b, u, s)))
+    print(f"4096 boxes fp32: worst rel-L2 {worst:.3e}")
+    assert worst <= TOL["fp32"], worst
