@@ -134,6 +134,28 @@ sbp_status sbp_set_workspace(sbp_plan plan, void* device_ptr, size_t bytes);
 sbp_status sbp_solve(sbp_plan plan, const void* const* rho, void* const* phi,
                      const sbp_shear* params, void* stream);
 
+/* Size of the fixed device workspace that sbp_solve_static uses: 128 MiB, enough for a
+ * 256 x 256 x 256 box in either precision (a plan's need is sbp_workspace_size). */
+#define SBP_STATIC_WORKSPACE_BYTES (128u << 20)
+
+/* For callers that cannot allocate device memory while they solve: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, layout and result as
+ * sbp_solve, but the workspace is a fixed array of SBP_STATIC_WORKSPACE_BYTES that the library
+ * holds on each device until the process ends (set up by sbp_plan_create on that device), so the
+ * call makes no hipMalloc, hipFree or other allocating call; the plan's own workspace and one set
+ * by sbp_set_workspace are not used.  It records no profiling events.
+ *   - SBP_E_SIZE if the plan needs more workspace than the array holds;
+ *   - SBP_E_STATE for an SBP_FLAG_GRAPH plan whose graph has not been captured yet (its first
+ *     sbp_solve captures it);
+ *   - SBP_E_HIP if the array's device address could not be obtained on the plan's device;
+ *   - SBP_E_ARG as sbp_solve, and if rho or phi overlaps the array.
+ * Every call on one device shares that device's array and leaves its contents behind; nothing in
+ * it needs to start at zero (a solve writes every workspace value before it reads it).  Calls that
+ * overlap in time on one device (other streams, or other host threads) race on the array and
+ * must be serialised by the caller. */
+sbp_status sbp_solve_static(sbp_plan plan, const void* const* rho, void* const* phi, const sbp_shear* params,
+                            void* stream);
+
 /* Potential with ng ghost layers below and above the box (Sect. 2.4): in the ghost cells the
  * vertical gradient equals that of the last active cell, i.e. Phi continues linearly with the
  * slope between the two outermost active cells.

@@ -112,6 +112,14 @@ class Plan:
     def solve(self, rho, phi, shear: Union[Shear, Sequence[Shear]], stream=None) -> None:
         """Enqueue one solve: rho, phi are device tensors (or lists, one per box) of shape
         (nx, ny, nz), C-contiguous, float32 for fp32 plans and float64 for fp64 plans."""
+        self._solve(self._lib.sbp_solve, "sbp_solve", rho, phi, shear, stream)
+
+    def solve_static(self, rho, phi, shear: Union[Shear, Sequence[Shear]], stream=None) -> None:
+        """As solve, through sbp_solve_static: the workspace is the library's fixed per-device
+        array, so the call allocates nothing (see include/sbp.h for its limits)."""
+        self._solve(self._lib.sbp_solve_static, "sbp_solve_static", rho, phi, shear, stream)
+
+    def _solve(self, fn, what, rho, phi, shear, stream) -> None:
         import torch
 
         rhos = [rho] if not isinstance(rho, (list, tuple)) else list(rho)
@@ -132,7 +140,7 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream(rhos[0].device)
         st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        _check(self._lib.sbp_solve(self._h, rp, pp, sp, ctypes.c_void_p(st)), "sbp_solve")
+        _check(fn(self._h, rp, pp, sp, ctypes.c_void_p(st)), what)
 
     # -- output for the hydrodynamics ------------------------------------------------------
     def _check_tensors(self, groups, shapes):

@@ -19,7 +19,8 @@ SBP_FLAG_GRAPH, SBP_FLAG_AUTOTUNE, SBP_FLAG_PLAIN, SBP_FLAG_FIVE_PASS, SBP_FLAG_
 # every symbol include/sbp.h declares
 EXPORTS = ("sbp_plan_create", "sbp_workspace_size", "sbp_set_workspace", "sbp_solve", "sbp_plan_destroy",
            "sbp_status_str", "sbp_last_error", "sbp_profile_enable", "sbp_profile_read", "sbp_plan_describe",
-           "sbp_ghosts", "sbp_gravity")
+           "sbp_ghosts", "sbp_gravity", "sbp_solve_static")
+SBP_STATIC_WORKSPACE_BYTES = 128 << 20
 
 
 class SbpBox(ctypes.Structure):
@@ -54,6 +55,8 @@ def load() -> ctypes.CDLL:
     lib.sbp_set_workspace.restype = ctypes.c_int
     lib.sbp_solve.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(SbpShear), P]
     lib.sbp_solve.restype = ctypes.c_int
+    lib.sbp_solve_static.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(SbpShear), P]
+    lib.sbp_solve_static.restype = ctypes.c_int
     lib.sbp_plan_destroy.argtypes = [P]
     lib.sbp_plan_destroy.restype = ctypes.c_int
     lib.sbp_status_str.argtypes = [ctypes.c_int]

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -41,6 +42,34 @@ struct ProfRec {
 
 const char* kPassName[8] = {"y_forward", "x_forward", "z_green", "x_inverse", "y_inverse",
                             "fused_a", "fused_b", "fused_c"};
+
+}  // namespace
+
+// Fixed workspace of sbp_solve_static: one array per device, held until the process ends.  In
+// host code this name is only a stand-in for the symbol; the device address comes from
+// hipGetSymbolAddress (static_scratch_setup) and only that address is ever used.
+static __device__ __align__(256) unsigned char scratch[SBP_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};        // device address of `scratch`, per device
+bool g_scratch_tried[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Resolve the device address of `scratch` on `device`, once per device; the device must be
+// current.  A failure is kept and reported by sbp_solve_static (other entry points still work).
+void static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+}
 
 }  // namespace
 
@@ -477,15 +506,16 @@ void destroy_graph(sbp_plan p) {
   p->graph = nullptr;
 }
 
-// workspace pointers in the record templates
-void bind_workspace(sbp_plan p) {
+// workspace pointers in the record templates, for the workspace at `ws`
+void bind_workspace(sbp_plan p, char* ws) {
   if (p->flags & SBP_FLAG_PLAIN) {
-    p->master[0].W = p->ws + p->boxes[0].ws2_off;
-    p->master[1].W = p->ws + p->boxes[0].ws_off;
+    p->master[0].W = ws + p->boxes[0].ws2_off;
+    p->master[1].W = ws + p->boxes[0].ws_off;
     return;
   }
-  for (size_t b = 0; b < p->boxes.size(); ++b) p->master[b].W = p->ws + p->boxes[b].ws_off;
+  for (size_t b = 0; b < p->boxes.size(); ++b) p->master[b].W = ws + p->boxes[b].ws_off;
 }
+void bind_workspace(sbp_plan p) { bind_workspace(p, p->ws); }
 
 // the records of one solve: the plan's templates with the per-solve fields filled in
 void fill_records(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, sbp::BoxRec* hs) {
@@ -719,6 +749,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
     p->prec = prec;
     p->flags = flags;
     HIP_TRY(hipSetDevice(device));
+    static_scratch_setup(device);
 
     TableBuilder tb;
     size_t ws = 0, npart = 0;
@@ -916,7 +947,15 @@ sbp_status sbp_set_workspace(sbp_plan p, void* ptr, size_t bytes) {
   return SBP_OK;
 }
 
-sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One solve of every box.  fixed_ws: take the workspace from the device's static array (the
+// allocation-free entry point) rather than the plan's own or the caller's; that path also makes
+// no event or stream of its own (no profiling records), so it allocates nothing.
+sbp_status solve_common(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, void* stream,
+                        bool fixed_ws) {
   try {
     if (!p) return fail(SBP_E_ARG, "NULL plan");
     if (!rho || !phi || !params) return fail(SBP_E_ARG, "NULL rho/phi/params array");
@@ -936,20 +975,40 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
       const double a = s.q * s.omega * p->boxes[b].g.lx * s.t;
       if (!std::isfinite(a) || !std::isfinite(s.G)) return fail(SBP_E_ARG, "box %zu: non-finite shear parameters", b);
     }
-    HIP_TRY(hipSetDevice(p->device));
-    if (!p->ws) {
-      void* d = nullptr;
-      if (hipMalloc(&d, std::max<size_t>(p->ws_need, 256)) != hipSuccess)
-        return fail(SBP_E_NOMEM, "workspace allocation (%zu bytes)", p->ws_need);
-      p->ws = (char*)d;
-      p->ws_owned = true;
+    char* ws = nullptr;
+    if (fixed_ws) {
+      if (p->ws_need > (size_t)SBP_STATIC_WORKSPACE_BYTES)
+        return fail(SBP_E_SIZE, "the plan needs %zu bytes of workspace; the static workspace holds %zu",
+                    p->ws_need, (size_t)SBP_STATIC_WORKSPACE_BYTES);
+      if ((p->flags & SBP_FLAG_GRAPH) && !p->gexec)
+        return fail(SBP_E_STATE, "the graph of this plan is captured by its first sbp_solve; call that first");
+      if (p->device >= kMaxDevices) return fail(SBP_E_ARG, "device %d has no static workspace", p->device);
+      {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ws = (char*)g_scratch_ptr[p->device];
+        if (!ws)
+          return fail(SBP_E_HIP, "static workspace unavailable on device %d: %s", p->device,
+                      g_scratch_tried[p->device] ? hipGetErrorString(g_scratch_err[p->device]) : "not set up");
+      }
+      HIP_TRY(hipSetDevice(p->device));
+    } else {
+      HIP_TRY(hipSetDevice(p->device));
+      if (!p->ws) {
+        void* d = nullptr;
+        if (hipMalloc(&d, std::max<size_t>(p->ws_need, 256)) != hipSuccess)
+          return fail(SBP_E_NOMEM, "workspace allocation (%zu bytes)", p->ws_need);
+        p->ws = (char*)d;
+        p->ws_owned = true;
+      }
+      ws = p->ws;
     }
     for (size_t b = 0; b < nb; ++b)
-      if (overlap(phi[b], p->boxes[b].data_bytes, p->ws, p->ws_need) ||
-          overlap(rho[b], p->boxes[b].data_bytes, p->ws, p->ws_need))
+      if (overlap(phi[b], p->boxes[b].data_bytes, ws, p->ws_need) ||
+          overlap(rho[b], p->boxes[b].data_bytes, ws, p->ws_need))
         return fail(SBP_E_ARG, "rho or phi of box %zu overlaps the workspace", b);
-    bind_workspace(p);
+    bind_workspace(p, ws);
     hipStream_t st = (hipStream_t)stream;
+    const bool prof = p->prof && !fixed_ws;
     if ((p->flags & SBP_FLAG_GRAPH) && !p->gexec) {
       // the replayed fetch kernel follows the device-side ring counter: start it and the host
       // ring at slot 0, once every earlier (direct, e.g. autotuning) use of the ring is done
@@ -964,7 +1023,7 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
       sbp::BoxRec recs[sbp::kArgRecs];
       fill_records(p, rho, phi, params, recs);
       Marker mk{p, st};
-      return enqueue(p, st, p->prof ? &mk : nullptr, 0, recs);
+      return enqueue(p, st, prof ? &mk : nullptr, 0, recs);
     }
     int slot = 0;
     sbp_status ss = stage_records(p, rho, phi, params, &slot);
@@ -988,13 +1047,13 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
       }
       // the replay fetches ring slot ctl[0], which advances in step with p->slot
       Marker mk{p, st};
-      if (p->prof) mk.mark("graph");
+      if (prof) mk.mark("graph");
       HIP_TRY(hipGraphLaunch(p->gexec, st));
-      if (p->prof) mk.mark(nullptr);
+      if (prof) mk.mark(nullptr);
       return commit_slot(p, slot, st);
     }
     Marker mk{p, st};
-    sbp_status es = enqueue(p, st, p->prof ? &mk : nullptr, slot);
+    sbp_status es = enqueue(p, st, prof ? &mk : nullptr, slot);
     if (es != SBP_OK) return es;
     return commit_slot(p, slot, st);
   } catch (const std::bad_alloc&) {
@@ -1002,6 +1061,19 @@ sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const
   } catch (...) {
     return fail(SBP_E_STATE, "internal error");
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+sbp_status sbp_solve(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params, void* stream) {
+  return solve_common(p, rho, phi, params, stream, false);
+}
+
+sbp_status sbp_solve_static(sbp_plan p, const void* const* rho, void* const* phi, const sbp_shear* params,
+                            void* stream) {
+  return solve_common(p, rho, phi, params, stream, true);
 }
 
 sbp_status sbp_ghosts(sbp_plan p, const void* const* phi, void* const* out, int32_t ng, void* stream) {
