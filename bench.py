@@ -66,7 +66,12 @@ LEGS = (("fp32", "fp32", False, False, "spectral", False), ("fp32_graph", "fp32"
         ("fp32_linear", "fp32", False, False, "linear", False))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grf256_fp32.json")
+# Summaries of rocprofv3 runs of this benchmark's FP32 leg (see each file for its command), keyed
+# by pass; each is valid only while the kernel sources hash to its sources_sha256.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_passes_grf256_fp32_traffic.json")
+TRACE_FILE = os.path.join(ROOT, "profiles", "fused_passes_grf256_fp32_trace.json")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "fused_passes_grf256_fp32_sq.json")
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 1024 SIMDs, 4 cycles each, 2.4 GHz
 
 
 def kernel_source_digest(files) -> str:
@@ -79,18 +84,25 @@ def kernel_source_digest(files) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, scaled by the plain-copy
-    calibration; None when no summary exists or the kernel's sources changed since it was taken."""
+def _profile(path: str, kernel: str):
+    """The record of `kernel` in a committed profile summary, or None when there is none or the
+    kernel sources have changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
     if not k or kernel_source_digest(rec["sources"]) != rec["sources_sha256"]:
         return None
-    return int(round((k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024))
+    return k
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel`: the L2-to-memory requests rocprofv3 counted, each weighed
+    by its own size (TCC_EA0_RDREQ_32B/64B/128B, TCC_EA0_WRREQ/WRREQ_64B); None if not current."""
+    k = _profile(TRAFFIC_FILE, kernel)
+    return None if k is None else int(k["read_bytes"] + k["write_bytes"])
 
 
 def copy_calibration(mib: int, steps: int) -> int:
@@ -114,6 +126,24 @@ def copy_calibration(mib: int, steps: int) -> int:
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": round(ms, 5),
                       "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
     return 0
+
+
+def host_cpu() -> dict:
+    """CPU model and core counts of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable, "threads_used": 1}
 
 
 def main() -> int:
@@ -269,9 +299,12 @@ def main() -> int:
         med = float(np.median(times))
         cpu = {"value": round(1.0 / med, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": f"{len(times)} full 256^3 FP64 oracle solves of the same input (numpy, one thread), "
-                         f"{sum(times):.1f} s in total, median {med:.2f} s per solve"}
+                         f"{sum(times):.1f} s in total, median {med:.2f} s per solve",
+               "host": host_cpu()}
 
-    # roofline of the dominant kernel of the headline (FP32) leg
+    # roofline of the dominant kernel of the headline (FP32) leg: HBM, with the kernel's duration
+    # from HIP events around each launch in this run (avg_us) and, beside it, the mean duration the
+    # committed kernel trace of the same leg records (no event between launches)
     k = res["fp32_direct"]["kernels"]
     name, (launches, tot) = max(k.items(), key=lambda kv: kv[1][1])
     avg_ms = tot / launches
@@ -280,6 +313,31 @@ def main() -> int:
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
             "avg_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": per_launch_bytes}
+    tr = _profile(TRACE_FILE, name)
+    if tr is not None:
+        roof["avg_us_trace"] = round(tr["mean_ns"] * 1e-3, 2)
+        roof["frac_trace"] = round(per_launch_bytes / (tr["mean_ns"] * 1e-9) / 1e9 / HBM_PEAK_GBS, 4)
+    sq = _profile(COUNTER_FILE, name)
+    if sq is not None:
+        # the same kernel against the VALU issue limit, which bounds it: committed instruction count
+        # over this run's duration, against 1024 SIMDs x one wave64 instruction per 4 cycles at 2.4 GHz
+        roof["valu"] = {"insts_per_launch": sq["SQ_INSTS_VALU"],
+                        "issue_frac": round(sq["SQ_INSTS_VALU"] / (avg_ms * 1e-3) / VALU_ISSUE_PEAK, 4)}
+
+    # the three byte counts of one FP32 solve: algorithmic (3 HBM round trips of the half spectrum),
+    # the schedule's model, and what the counters recorded for the three passes
+    fp32_b_alg = 6 * N * 4
+    sched = res["fp32"]["describe"].get("bytes_model")
+    counted = [measured_traffic(kk) for kk in ("fused_a", "fused_b", "fused_c")]
+    counted = sum(counted) if all(c is not None for c in counted) else None
+    t_s = res["fp32"]["ms"] * 1e-3
+    bytes_per_solve = {"algorithmic": fp32_b_alg, "schedule_model": sched, "counters": counted,
+                       "gbs_algorithmic": round(fp32_b_alg / t_s / 1e9, 1),
+                       "gbs_schedule_model": round(sched / t_s / 1e9, 1) if sched else None,
+                       "gbs_counters": round(counted / t_s / 1e9, 1) if counted else None,
+                       "counters_note": "L2-to-memory requests of the three passes weighed by their size, from the "
+                                        "committed summary; they include hits in the 256 MB MALL, which the counters "
+                                        "available on gfx950 do not separate from HBM"}
 
     head = res["fp32"]
     out = {
@@ -324,6 +382,7 @@ def main() -> int:
                        for leg in res if res[leg]["kernels"]},
         "schedule": head["describe"],
         "roofline": roof,
+        "bytes_per_solve": bytes_per_solve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -68,7 +68,9 @@ typedef enum { SBP_REMAP_SPECTRAL = 0, SBP_REMAP_LINEAR = 1 } sbp_remap;
 
 /* Plan flags. */
 #define SBP_FLAG_GRAPH 0x1u    /* capture the solve once into a HIP graph; replay per call      */
-#define SBP_FLAG_AUTOTUNE 0x2u /* time the tile variants at plan creation and keep the fastest */
+#define SBP_FLAG_AUTOTUNE 0x2u /* time the tile variants at plan creation and keep the fastest
+                                  (five-pass kernels, fused passes A and C); results are cached in
+                                  the file named by SBP_TUNE_CACHE ($HOME/.cache/sbp_tune.txt) */
 #define SBP_FLAG_PLAIN 0x4u    /* unfused reference path: padded spectrum in HBM, one kernel per
                                   step (pad, each axis transform, Green multiply, extract, ...) */
 #define SBP_FLAG_FIVE_PASS 0x8u /* one streaming pass per axis and direction: five HBM round trips

@@ -562,11 +562,20 @@ std::string describe_plan(sbp_plan p) {
   s += (p->flags & SBP_FLAG_PLAIN) ? "plain" : (any_fused ? (any_five ? "mixed" : "fused-3pass") : "streaming-5pass");
   s += "\",\"precision\":\"";
   s += p->prec ? "fp32" : "fp64";
-  char buf[320];
+  // modelled HBM bytes of one solve (data arrays only): each pass reads and writes N w bytes, three
+  // passes fused, five streaming; the plain path's eleven steps touch the padded spectrum (P N w)
+  // in six of them: 12 + 10 P
+  double model = 0.0;
+  for (const BoxInfo& b : p->boxes) {
+    const double nw = (double)b.g.nx * b.g.ny * b.g.nz * elem_size(p->prec);
+    model += nw * ((p->flags & SBP_FLAG_PLAIN) ? 12.0 + 10.0 * b.pad : b.fused ? 6.0 : 10.0);
+  }
+  char buf[400];
   snprintf(buf, sizeof buf,
-           "\",\"nbox\":%zu,\"launches\":%zu,\"graph\":%s,\"workspace_bytes\":%zu,\"tuning\":\"%s\"",
+           "\",\"nbox\":%zu,\"launches\":%zu,\"graph\":%s,\"workspace_bytes\":%zu,\"tuning\":\"%s\","
+           "\"bytes_model\":%.0f",
            p->boxes.size(), (p->flags & SBP_FLAG_PLAIN) ? (size_t)13 : p->launches.size(),
-           (p->flags & SBP_FLAG_GRAPH) ? "true" : "false", p->ws_need, p->tune_source.c_str());
+           (p->flags & SBP_FLAG_GRAPH) ? "true" : "false", p->ws_need, p->tune_source.c_str(), model);
   s += buf;
   s += ",\"groups\":[";
   for (size_t i = 0; i < p->launches.size(); ++i) {
