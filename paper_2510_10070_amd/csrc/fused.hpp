@@ -243,14 +243,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
 // of its own box's A with that box's x twiddles, so one launch covers what would otherwise be
 // one small launch per A.  Registers and LDS are those of the largest body.
 template <typename T, int NY, int B, int V, bool LIN>
-__global__ __launch_bounds__(kFusedAC) void k_fa_mix(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                                     const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
-  constexpr int NT = fa_threads<V>();
-  __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, false>()];
-  __shared__ cplx<T> tw[NY];
-  __shared__ double red[2 * (NT / 64)];
-  int t;
-  const BoxRec* br = group_box(ga, recs, t);
+__device__ __forceinline__ void fa_mix_body(const BoxRec* br, int t, const cplx<T>* __restrict__ twy, cplx<T>* tile,
+                                            cplx<T>* tw, double* red) {
   const cplx<T>* twx = static_cast<const cplx<T>*>(br->twx);
   switch (br->g.nx / B) {
     case 1: fa_body<T, NY, 1, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
@@ -259,6 +253,18 @@ __global__ __launch_bounds__(kFusedAC) void k_fa_mix(GroupArgs ga, const BoxRec*
     case 6: fa_body<T, NY, 6, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
     default: fa_body<T, NY, 8, B, V, LIN>(br, t, twy, twx, tile, tw, red); break;
   }
+}
+
+template <typename T, int NY, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fa_mix(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                     const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
+  constexpr int NT = fa_threads<V>();
+  __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, false>()];
+  __shared__ cplx<T> tw[NY];
+  __shared__ double red[2 * (NT / 64)];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  fa_mix_body<T, NY, B, V, LIN>(br, t, twy, tile, tw, red);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -416,12 +422,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
 
 // Pass C for a launch group whose boxes differ in Nx (A <= 8), as k_fa_mix
 template <typename T, int NY, int B, int V, bool LIN>
-__global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                                     const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
-  __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, true>()];
-  __shared__ cplx<T> tw[NY];
-  int t;
-  const BoxRec* br = group_box(ga, recs, t);
+__device__ __forceinline__ void fc_mix_body(const BoxRec* br, int t, const cplx<T>* __restrict__ twy, cplx<T>* tile,
+                                            cplx<T>* tw) {
   const cplx<T>* twx = static_cast<const cplx<T>*>(br->twx);
   switch (br->g.nx / B) {
     case 1: fc_body<T, NY, 1, B, V, LIN>(br, t, twy, twx, tile, tw); break;
@@ -429,6 +431,65 @@ __global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec*
     case 4: fc_body<T, NY, 4, B, V, LIN>(br, t, twy, twx, tile, tw); break;
     case 6: fc_body<T, NY, 6, B, V, LIN>(br, t, twy, twx, tile, tw); break;
     default: fc_body<T, NY, 8, B, V, LIN>(br, t, twy, twx, tile, tw); break;
+  }
+}
+
+template <typename T, int NY, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                     const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
+  __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, true>()];
+  __shared__ cplx<T> tw[NY];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  fc_mix_body<T, NY, B, V, LIN>(br, t, twy, tile, tw);
+}
+
+// Passes A and C for a launch group whose boxes differ in Ny <= 128 as well as in A <= 8 (float,
+// 64-byte rows): every block runs the body of its own box's Ny and A with that box's y and x
+// twiddles, so the groups of a batch that would each be one launch per Ny share one, and their
+// blocks fill the chip together.  Registers and LDS are those of the largest body (Ny = 128).
+constexpr int kMultiNyMax = 128;
+template <typename T, int V, bool C> constexpr int ac_multi_tile() {
+  constexpr int t[5] = {ac_mix_tile<T, 16, V, C>(), ac_mix_tile<T, 32, V, C>(), ac_mix_tile<T, 64, V, C>(),
+                        ac_mix_tile<T, 96, V, C>(), ac_mix_tile<T, 128, V, C>()};
+  int m = 0;
+  for (int v : t) m = v > m ? v : m;
+  return m;
+}
+
+template <typename T, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fa_multi(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                       const cplx<T>* __restrict__, const cplx<T>* __restrict__) {
+  constexpr int NT = fa_threads<V>();
+  __shared__ cplx<T> tile[ac_multi_tile<T, V, false>()];
+  __shared__ cplx<T> tw[kMultiNyMax];
+  __shared__ double red[2 * (NT / 64)];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
+  switch (br->g.ny) {
+    case 16: fa_mix_body<T, 16, B, V, LIN>(br, t, twy, tile, tw, red); break;
+    case 32: fa_mix_body<T, 32, B, V, LIN>(br, t, twy, tile, tw, red); break;
+    case 64: fa_mix_body<T, 64, B, V, LIN>(br, t, twy, tile, tw, red); break;
+    case 96: fa_mix_body<T, 96, B, V, LIN>(br, t, twy, tile, tw, red); break;
+    default: fa_mix_body<T, 128, B, V, LIN>(br, t, twy, tile, tw, red); break;
+  }
+}
+
+template <typename T, int B, int V, bool LIN>
+__global__ __launch_bounds__(kFusedAC) void k_fc_multi(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                       const cplx<T>* __restrict__, const cplx<T>* __restrict__) {
+  __shared__ cplx<T> tile[ac_multi_tile<T, V, true>()];
+  __shared__ cplx<T> tw[kMultiNyMax];
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
+  switch (br->g.ny) {
+    case 16: fc_mix_body<T, 16, B, V, LIN>(br, t, twy, tile, tw); break;
+    case 32: fc_mix_body<T, 32, B, V, LIN>(br, t, twy, tile, tw); break;
+    case 64: fc_mix_body<T, 64, B, V, LIN>(br, t, twy, tile, tw); break;
+    case 96: fc_mix_body<T, 96, B, V, LIN>(br, t, twy, tile, tw); break;
+    default: fc_mix_body<T, 128, B, V, LIN>(br, t, twy, tile, tw); break;
   }
 }
 

@@ -97,6 +97,32 @@ SBP_FUSED_NY(SBP_EXTERN_AC_D)
 #undef SBP_EXTERN_AC_F
 #undef SBP_EXTERN_AC_D
 
+// passes A (kind 0) and C (kind 2) for a group that mixes Ny <= 128 and A <= 8 (float, variant 1;
+// instantiated in fused_f32_multi.hip)
+template <typename T>
+hipError_t launch_ac_multi(int kind, bool lin, GroupArgs ga, int blocks, const BoxRec* recs, hipStream_t st);
+extern template hipError_t launch_ac_multi<float>(int, bool, GroupArgs, int, const BoxRec*, hipStream_t);
+
+template <typename T>
+hipError_t launch_ac_multi(int kind, bool lin, GroupArgs ga, int blocks, const BoxRec* recs, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    constexpr int B = kFusedB16;
+    const dim3 grid(blocks), block(fa_threads<1>());
+    const cplx<T>* none = nullptr;
+    if (kind == 0) {
+      if (lin) hipLaunchKernelGGL((k_fa_multi<T, B, 1, true>), grid, block, 0, st, ga, recs, none, none);
+      else hipLaunchKernelGGL((k_fa_multi<T, B, 1, false>), grid, block, 0, st, ga, recs, none, none);
+    } else {
+      if (lin) hipLaunchKernelGGL((k_fc_multi<T, B, 1, true>), grid, block, 0, st, ga, recs, none, none);
+      else hipLaunchKernelGGL((k_fc_multi<T, B, 1, false>), grid, block, 0, st, ga, recs, none, none);
+    }
+    return hipGetLastError();
+  } else {
+    (void)kind; (void)lin; (void)ga; (void)blocks; (void)recs; (void)st;
+    return hipErrorInvalidValue;
+  }
+}
+
 // the launcher of one precision: pass B here, passes A and C in their own translation units
 template <typename T>
 hipError_t launch_fused_dispatch(int kind, int len, int a, int q, int variant, bool lin, GroupArgs ga, int blocks,
@@ -116,6 +142,11 @@ hipError_t launch_fused_dispatch(int kind, int len, int a, int q, int variant, b
     return hipErrorInvalidValue;
   }
   const cplx<T>* t2 = static_cast<const cplx<T>*>(tw2);
+  if (len == 0) {
+    // a group mixing Ny: float 64-byte rows only, every block takes its box's twiddles
+    if (sizeof(T) != 4 || variant != 1 || a != 0) return hipErrorInvalidValue;
+    return launch_ac_multi<T>(kind, lin, ga, blocks, recs, st);
+  }
 #define SBP_CASE(NY_) \
   if (len == NY_) return launch_ac_ny<T, NY_>(kind, a, variant, lin, ga, blocks, recs, t1, t2, st);
   SBP_FUSED_NY(SBP_CASE)

@@ -45,6 +45,7 @@ struct BoxRec {
   const double* zt64[3]; // the three columns separately in double
   const double* k0h;     // k = 0 pencil in real space: h[n] = sum_m G(0, kz_m) cos(2 pi m n/M)
   const void* twx;       // x twiddles w_Nx^m, m < Nx, plan precision (fused passes A and C)
+  const void* twy;       // stage-major y twiddles of Ny (fused passes A and C of groups mixing Ny)
 };
 
 // Pointers held in the records and launch arguments address device global memory.  Kernels

@@ -397,6 +397,21 @@ void build_launches(sbp_plan p) {
         }
         std::sort(merged.begin(), merged.end());
       }
+      // and groups of 64-byte rows that differ in Ny <= 128 as well: one launch (len = 0) for all
+      std::map<int, std::vector<std::tuple<int, int, int, int, int>>> multi;  // lin -> group keys
+      for (auto& kv : groups) {
+        const auto& [len, var, q, a, lin] = kv.first;
+        if (var == 1 && len > 0 && len <= 128 && a <= 8) multi[lin].push_back(kv.first);
+      }
+      for (auto& mv : multi) {
+        if (mv.second.size() < 2) continue;
+        std::vector<int>& merged = groups[std::make_tuple(0, 1, 0, 0, mv.first)];
+        for (const auto& key : mv.second) {
+          merged.insert(merged.end(), groups[key].begin(), groups[key].end());
+          groups.erase(key);
+        }
+        std::sort(merged.begin(), merged.end());
+      }
     }
     for (auto& kv : groups) {
       Launch l;
@@ -884,6 +899,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       rec.zt = p->d_tables + bi.zt;
       rec.k0h = (const double*)(p->d_tables + bi.k0h);
       rec.twx = p->d_tables + bi.tw_x;
+      rec.twy = p->d_tables + bi.tws_y;
       for (int k = 0; k < 3; ++k) rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
     }
 

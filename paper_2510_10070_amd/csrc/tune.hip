@@ -190,12 +190,12 @@ sbp_status autotune(sbp_plan p) {
   }
 
   // The per-key choices were timed group by group with every (Ny, A) in a launch of its own, but
-  // float plans merge the boxes of one Ny with A <= 8 and 64-byte rows (the default) into one
-  // launch.  Where that merging happens, whether the per-key choices beat the defaults is a
+  // float plans merge the boxes with A <= 8 and 64-byte rows (the default), of any Ny <= 256 and
+  // across Ny <= 128, into few launches.  Where that merging happens, whether the per-key choices beat the defaults is a
   // property of the whole plan: time both once (per set of fused box shapes, cached) and keep
   // the faster.
   bool differs = false;
-  std::map<std::pair<int, int>, std::set<int>> mixed;  // (Ny, remap) -> A of the boxes merged by default
+  std::map<int, std::set<int>> mixed;  // remap -> (Ny, A) of the boxes merged by default
   uint32_t sig = 2166136261u;  // FNV-1a over the fused boxes' kernel shapes
   auto mix = [&](uint32_t v) {
     for (int i = 0; i < 4; ++i) {
@@ -208,14 +208,14 @@ sbp_status autotune(sbp_plan p) {
     int dv[kKinds];
     default_variants(prec, b.g, dv);
     differs = differs || b.var[kFA] != dv[kFA] || b.var[kFC] != dv[kFC];
-    if (dv[kFA] == 1) mixed[std::make_pair(b.g.ny, b.g.remap)].insert(b.g.nx / 16);
+    if (dv[kFA] == 1) mixed[b.g.remap].insert(1000 * b.g.ny + b.g.nx / 16);
     mix((uint32_t)b.g.nx);
     mix((uint32_t)b.g.ny);
     mix((uint32_t)b.g.nz);
     mix((uint32_t)b.pad);
     mix((uint32_t)b.g.remap);
   }
-  bool merges = false;  // a default launch would serve boxes of several A
+  bool merges = false;  // a default launch would serve boxes of several (Ny, A)
   for (auto& kv : mixed) merges = merges || kv.second.size() > 1;
   if (differs && merges) {
     const Key pk(arch, prec, kPlanChoice, (int)(sig & 0x7fffffffu), (int)boxes.size());

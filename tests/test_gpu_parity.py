@@ -233,6 +233,30 @@ def test_mixed_nx_launch_groups_fp32(remap):
         assert rel_l2(g, oracle_solve(b, u, s)) <= TOL["fp32"], b
 
 
+@pytest.mark.parametrize("remap", ["spectral", "linear"])
+def test_mixed_ny_launch_groups_fp32(remap):
+    # FP32 passes A and C also run boxes of different Ny <= 128 (and A <= 8) in one launch, every
+    # block taking its box's Ny, A and twiddles from the record; boxes of Ny = 256 keep their own
+    shapes = [(16, 16, 16), (32, 32, 16), (64, 64, 16), (96, 96, 16), (128, 128, 16), (32, 96, 16), (64, 16, 16),
+              (128, 32, 16)]
+    boxes = [dict(_box(s + (1.0 + 0.1 * i, 1.0 + 0.05 * i, 1.0, 2, 0.0), "sasha" if i % 3 == 1 else "vgf"), remap=remap)
+             for i, s in enumerate(shapes)]
+    from paper_2510_10070_amd import Box, Plan
+
+    plan = Plan([Box(**b) for b in boxes], precision="fp32", schedule="fused")
+    d = plan.describe()
+    plan.close()
+    assert d["launches"] == 3, d  # pass A, pass B (one M), pass C
+    rhos = [lognormal_density(s, 1.0, 0.2, seed=140 + i) for i, s in enumerate(shapes)]
+    shears = [(1.5, 1.0, 0.15 + 0.1 * i, 1.0) for i in range(len(shapes))]
+    for graph in (False, True):
+        got, used = gpu_solve(boxes, rhos, shears, "fp32", schedule="fused", graph=graph)
+        for b, g, u, s in zip(boxes, got, used, shears):
+            ref = oracle_solve(b, u, s)
+            assert rel_l2(g, ref) <= TOL["fp32"], b
+            assert per_mode_error(g, ref) <= TOL["fp32"], b
+
+
 # shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 6, 8, 16}, y up to
 # 512, padded z from 32 to 512 and 192, P in {2, 4}; float boxes with nx <= 128 and ny <= 256 take
 # 64-byte rows (16 z cells), so nz = 8 leaves a ragged tile
