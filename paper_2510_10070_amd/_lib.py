@@ -6,7 +6,11 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsbp.so")
+# SBP_LIBRARY_VARIANT=poison or asan loads a debug build of the same sources (see build.py)
+_VARIANT = os.environ.get("SBP_LIBRARY_VARIANT", "")
+if _VARIANT not in ("", "default", "poison", "asan"):
+    raise RuntimeError(f"SBP_LIBRARY_VARIANT={_VARIANT!r}: expected poison or asan")
+LIB_PATH = os.path.join(_HERE, "libsbp.so" if _VARIANT in ("", "default") else f"libsbp_{_VARIANT}.so")
 
 SBP_OK = 0
 STATUS_NAMES = {0: "SBP_OK", 1: "SBP_E_ARG", 2: "SBP_E_SIZE", 3: "SBP_E_NOMEM", 4: "SBP_E_WORKSPACE",

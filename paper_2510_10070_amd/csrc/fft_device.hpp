@@ -585,6 +585,23 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __res
   for (int i = tid; i < COUNT; i += NT) dst[STRIDE * i + OFF] = src[i];
 }
 
+// Debug builds (SBP_POISON_LDS defined) fill a kernel's shared arrays with a quiet NaN before any
+// thread uses them, so that a read of an element that no thread wrote turns the result into NaN,
+// which the parity tests catch.  The barrier makes the fill complete before first use.  In
+// other builds this is empty.
+template <class... A> __device__ __forceinline__ void lds_poison(A&... arrays) {
+#ifdef SBP_POISON_LDS
+  auto fill = [](auto& a) {
+    unsigned* w = reinterpret_cast<unsigned*>(&a);
+    for (unsigned i = threadIdx.x; i < sizeof(a) / 4; i += blockDim.x) w[i] = 0x7fc00000u;
+  };
+  (fill(arrays), ...);
+  __syncthreads();
+#else
+  ((void)arrays, ...);
+#endif
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each XCD
 // a contiguous range of the T tiles so that tiles sharing cache lines run on the same L2 at
 // about the same time.

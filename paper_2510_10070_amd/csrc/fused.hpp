@@ -234,6 +234,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   __shared__ cplx<T> tile[S::TILE];
   __shared__ cplx<T> tw[NY];
   __shared__ double red[2 * (S::NT / 64)];
+  lds_poison(tile, tw, red);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   fa_body<T, NY, A, B, V, LIN>(br, t, twy, twx, tile, tw, red);
@@ -262,6 +263,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa_mix(GroupArgs ga, const BoxRec*
   __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, false>()];
   __shared__ cplx<T> tw[NY];
   __shared__ double red[2 * (NT / 64)];
+  lds_poison(tile, tw, red);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   fa_mix_body<T, NY, B, V, LIN>(br, t, twy, tile, tw, red);
@@ -415,6 +417,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc(GroupArgs ga, const BoxRec* __r
                                                  const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twx) {
   __shared__ cplx<T> tile[AcShape<T, NY, A, V, true>::TILE];
   __shared__ cplx<T> tw[NY];
+  lds_poison(tile, tw);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   fc_body<T, NY, A, B, V, LIN>(br, t, twy, twx, tile, tw);
@@ -439,6 +442,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec*
                                                      const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__) {
   __shared__ cplx<T> tile[ac_mix_tile<T, NY, V, true>()];
   __shared__ cplx<T> tw[NY];
+  lds_poison(tile, tw);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   fc_mix_body<T, NY, B, V, LIN>(br, t, twy, tile, tw);
@@ -464,6 +468,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fa_multi(GroupArgs ga, const BoxRe
   __shared__ cplx<T> tile[ac_multi_tile<T, V, false>()];
   __shared__ cplx<T> tw[kMultiNyMax];
   __shared__ double red[2 * (NT / 64)];
+  lds_poison(tile, tw, red);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
@@ -481,6 +486,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fc_multi(GroupArgs ga, const BoxRe
                                                        const cplx<T>* __restrict__, const cplx<T>* __restrict__) {
   __shared__ cplx<T> tile[ac_multi_tile<T, V, true>()];
   __shared__ cplx<T> tw[kMultiNyMax];
+  lds_poison(tile, tw);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
@@ -518,6 +524,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __
   __shared__ cplx<T> tile[PG * SLOTS];
   __shared__ cplx<T> tw[NY];
   __shared__ double red[2][NT / 64];
+  lds_poison(tile, tw, red);
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -634,6 +641,7 @@ __global__ __launch_bounds__(kFusedAC) void k_fcs(GroupArgs ga, const BoxRec* __
   using L = Tile<NB, NB, 1, true>;
   __shared__ cplx<T> tile[PG * SLOTS];
   __shared__ cplx<T> tw[NY];
+  lds_poison(tile, tw);
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -1078,6 +1086,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_pe
   constexpr int WV = fb_waves<M, B, Q>();
   constexpr int NT = 64 * WV;
   __shared__ FbShared<T, M, B, Q> sh;
+  lds_poison(sh);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const int tid = threadIdx.x;

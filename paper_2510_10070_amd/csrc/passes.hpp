@@ -173,6 +173,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   __shared__ cplx<T> tw[NY];
   __shared__ cplx<T> ph[NY / 2];
   __shared__ double red[2][NT / 64];
+  lds_poison(tile, tw, ph, red);
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -281,6 +282,7 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
   __shared__ cplx<T> tile[pad_slots<PAD>(NY * NB)];
   __shared__ cplx<T> tw[NY];
   __shared__ cplx<T> ph[NY / 2];
+  lds_poison(tile, tw, ph);
 
   int t;
   const BoxRec* br = group_box(ga, recs, t);
@@ -384,6 +386,7 @@ __global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* 
   using L = Tile<ZC, ZC, 1, true, PAD>;
   __shared__ cplx<T> buf[pad_slots<PAD>(NX * ZC)];
   __shared__ cplx<T> tw[NX];
+  lds_poison(buf, tw);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const BoxGeom g = br->g;
@@ -435,10 +438,12 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   using LW = Tile<PW, 1, M, false, PAD>;
   constexpr int XS = pad_slots<PAD>(PW * M);
   __shared__ cplx<T> xbuf[WV * XS];
+  lds_poison(xbuf);
   // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
   constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
   __shared__ cplx<T> tw[kOneTw ? M : 2 * M];
   __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW], psp[WV][PPW];
+  lds_poison(tw, pa0, pe, pik, pk2, psp);
   // block-0 work before the wavefront transforms borrows xbuf (SASHA reduction, then the double
   // k = 0 exchange tile of float plans)
   static_assert(lds_slots(M) * 16 <= WV * XS * (int)sizeof(cplx<T>), "k = 0 tile must fit");

@@ -98,6 +98,7 @@ __global__ void k_plain_green(const BoxRec* __restrict__ rec, const BoxRec* __re
 // SASHA reductions: per-block sums of rho and z*rho (block b covers a strided subset)
 __global__ void k_plain_reduce(const BoxRec* __restrict__ rec) {
   __shared__ double red[2][kEw];
+  lds_poison(red);
   const BoxGeom g = rec->g;
   const double* rho = static_cast<const double*>(rec->rho);
   const size_t n = (size_t)g.nx * g.ny * g.nz;
@@ -168,6 +169,7 @@ __global__ __launch_bounds__(256) void k_plain_zfft(const BoxRec* __restrict__ p
   constexpr int PP = zplain_pp<M>();
   using L = Tile<PP, 1, M, false>;
   __shared__ double2 buf[lds_slots(PP * M)];
+  lds_poison(buf);
   const BoxGeom g = pad->g;
   const int npencils = g.nx * (g.ny / 2);
   const int p0 = blockIdx.x * PP;
