@@ -356,7 +356,8 @@ def main() -> int:
         "config": {"workload": "grf-256: one 256x256x256 box, Lx=Ly=4, Lz=6, H=1, z padded to 512, VGF-HybridBC, "
                                "q=1.5, Omega=1, t=0.3, G=1, FP32 bulk with FP64-derived Green coefficients, "
                                "twiddles and k=0 pencil, direct launches (per-solve shear staged in each call)",
-                   "global_batch": 1, "seq_len": None, "parallelism": "single-gpu"},
+                   "box": [nx, ny, nz], "padded_nz": 2 * nz, "precision": "fp32", "launch": "direct",
+                   "boxes_per_step": 1},
         "gbs_alg": round(head["gbs_alg"], 1),
         "hbm_frac_alg": round(head["gbs_alg"] / HBM_PEAK_GBS, 4),
         "rel_l2_vs_oracle": {k2: v for k2, v in errs.items()},
