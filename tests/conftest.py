@@ -9,6 +9,14 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # autotuned plans in the tests read and write a tune cache of their own, not the user's
+    if not os.environ.get("SBP_TUNE_CACHE"):
+        import tempfile
+
+        fd, path = tempfile.mkstemp(prefix="sbp_tune_tests_", suffix=".txt")
+        os.close(fd)
+        os.environ["SBP_TUNE_CACHE"] = path
+        config._sbp_tune_cache = path
     config.addinivalue_line("markers", "gpu: needs an AMD MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
 
@@ -27,3 +35,9 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+def pytest_unconfigure(config):
+    path = getattr(config, "_sbp_tune_cache", None)
+    if path and os.path.exists(path):
+        os.remove(path)
