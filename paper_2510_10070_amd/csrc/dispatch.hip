@@ -41,6 +41,11 @@ int fused_ac_tiles(int prec, const BoxGeom& g, int variant) {
 }
 int fused_b_tiles(const BoxGeom& g) { return (g.nx / kFusedB16) * (g.ny / 2); }
 int fused_a(const BoxGeom& g) { return g.nx / kFusedB16; }
+int fused_b_items_per_block(const BoxGeom& g, int pad) {
+  if (pad != 2 || g.m > kMultiMMax) return 0;
+  const int ipb = fb_multi_items_per_block(g.m);
+  return ipb > 0 && fused_b_tiles(g) % ipb == 0 ? ipb : 0;
+}
 hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st) {
   return prec ? launch_fused_impl<float>(kind, len, a, variant, q, lin, ga, blocks, recs, tw, tw2, st)

@@ -1107,6 +1107,86 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fb_waves_pe
   fb_dft_out<T, M, B, Q, NT>(sh, it, tid);
 }
 
+// Pass B for a launch group whose boxes differ in M <= 256 (float, padding 2): every block runs
+// the body of its own box's M with that box's z twiddles, so the groups of a batch that would
+// each be one launch per M share one, and their blocks overlap instead of each launch waiting
+// for its slowest block.  An item of M <= 128 needs fewer than four wavefronts: a block then
+// takes IPB consecutive items of its box, one per wavefront group, each with its own LDS part.
+constexpr int kMultiMMax = 256;
+template <int M, int B, int Q> constexpr int fb_multi_ipb() { return 4 / fb_waves<M, B, Q>(); }
+template <typename T, int M, int B, int Q> constexpr size_t fb_multi_bytes() {
+  return fb_multi_ipb<M, B, Q>() * sizeof(FbShared<T, M, B, Q>);
+}
+template <typename T, int B, int Q> constexpr size_t fb_multi_lds() {
+  constexpr size_t s[5] = {fb_multi_bytes<T, 32, B, Q>(), fb_multi_bytes<T, 64, B, Q>(), fb_multi_bytes<T, 128, B, Q>(),
+                           fb_multi_bytes<T, 192, B, Q>(), fb_multi_bytes<T, 256, B, Q>()};
+  size_t m = 0;
+  for (size_t v : s) m = v > m ? v : m;
+  return m;
+}
+// items per block of a box in such a group (host side: the box's block count is items / IPB)
+inline int fb_multi_items_per_block(int m) {
+  switch (m) {
+    case 32: return fb_multi_ipb<32, kFusedB16, 2>();
+    case 64: return fb_multi_ipb<64, kFusedB16, 2>();
+    case 128: return fb_multi_ipb<128, kFusedB16, 2>();
+    case 192: return fb_multi_ipb<192, kFusedB16, 2>();
+    case 256: return fb_multi_ipb<256, kFusedB16, 2>();
+    default: return 0;
+  }
+}
+
+template <typename T, int M, int B, int Q>
+__device__ __forceinline__ void fb_multi_body(const BoxRec* br, int t, cplx<T>* lds) {
+  constexpr int WV = fb_waves<M, B, Q>();
+  constexpr int NT = 64 * WV;
+  constexpr int IPB = fb_multi_ipb<M, B, Q>();
+  using Sh = FbShared<T, M, B, Q>;
+  static_assert(sizeof(Sh) % sizeof(cplx<T>) == 0, "item parts stay aligned");
+  const int sub = (int)threadIdx.x / NT, tid = (int)threadIdx.x - sub * NT;
+  Sh& sh = *reinterpret_cast<Sh*>(lds + sub * (sizeof(Sh) / sizeof(cplx<T>)));
+  const cplx<T>* twm = static_cast<const cplx<T>*>(br->twz);
+  const FbItem<T> it = fb_item<T, M, B, Q>(br, t * IPB + sub);
+  if constexpr (Sh::kTwReg) {
+    // each lane reads its own twiddles from HBM in fb_pencils
+  } else if constexpr (Sh::kHoles) {
+    load_twiddles<T, M - 1, NT, 9, 8>(sh.tile, twm, tid);
+  } else {
+    load_twiddles<T, Sh::kOneTw ? M : 2 * M, NT>(sh.tw, twm, tid);
+  }
+  fb_scalars(sh, it, br->g.nx / B, tid);
+  fb_dft_in<T, M, B, Q, NT>(sh, tid, [&](int jj, int z) { return it.base[(size_t)jj * (M / Q) + z]; });
+  __syncthreads();
+  fb_pencils<T, M, B, Q, WV>(sh, it, tid, twm);
+  __syncthreads();
+  fb_dft_out<T, M, B, Q, NT>(sh, it, tid);
+  // in float the k = 0 item passes three more workgroup barriers in fb_dft_out than the others:
+  // the other items of its block (t = 0) pass as many, so that every wavefront meets the same count
+  if constexpr (IPB > 1 && Sh::kF32) {
+    if (t == 0 && !it.own0) {
+      __syncthreads();
+      __syncthreads();
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, int B, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fb_multi(GroupArgs ga,
+                                                                                           const BoxRec* __restrict__ recs) {
+  __shared__ cplx<T> lds[fb_multi_lds<T, B, Q>() / sizeof(cplx<T>)];
+  lds_poison(lds);
+  int t;
+  const BoxRec* br = group_box(ga, recs, t);
+  switch (br->g.m) {
+    case 32: fb_multi_body<T, 32, B, Q>(br, t, lds); break;
+    case 64: fb_multi_body<T, 64, B, Q>(br, t, lds); break;
+    case 128: fb_multi_body<T, 128, B, Q>(br, t, lds); break;
+    case 192: fb_multi_body<T, 192, B, Q>(br, t, lds); break;
+    default: fb_multi_body<T, 256, B, Q>(br, t, lds); break;
+  }
+}
+
 template <typename T>
 hipError_t launch_fused_impl(int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                              const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);

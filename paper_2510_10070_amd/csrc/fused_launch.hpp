@@ -123,6 +123,20 @@ hipError_t launch_ac_multi(int kind, bool lin, GroupArgs ga, int blocks, const B
   }
 }
 
+// pass B for a group that mixes M <= 256 (float, padding 2; instantiated in fused_f32_multi.hip)
+template <typename T> hipError_t launch_fb_multi(GroupArgs ga, int blocks, const BoxRec* recs, hipStream_t st);
+extern template hipError_t launch_fb_multi<float>(GroupArgs, int, const BoxRec*, hipStream_t);
+
+template <typename T> hipError_t launch_fb_multi(GroupArgs ga, int blocks, const BoxRec* recs, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    hipLaunchKernelGGL((k_fb_multi<T, kFusedB16, 2>), dim3(blocks), dim3(256), 0, st, ga, recs);
+    return hipGetLastError();
+  } else {
+    (void)ga; (void)blocks; (void)recs; (void)st;
+    return hipErrorInvalidValue;
+  }
+}
+
 // the launcher of one precision: pass B here, passes A and C in their own translation units
 template <typename T>
 hipError_t launch_fused_dispatch(int kind, int len, int a, int q, int variant, bool lin, GroupArgs ga, int blocks,
@@ -131,6 +145,7 @@ hipError_t launch_fused_dispatch(int kind, int len, int a, int q, int variant, b
   const dim3 grid(blocks);
   const cplx<T>* t1 = static_cast<const cplx<T>*>(tw);
   if (kind == 1) {
+    if (len == 0) return launch_fb_multi<T>(ga, blocks, recs, st);
 #define SBP_CASE(M_)                                                                                                 \
     if (len == M_) {                                                                                                 \
       if (q == 4) hipLaunchKernelGGL((k_fb<T, M_, B, 4>), grid, dim3(fb_threads<M_, B, 4>()), 0, st, ga, recs, t1); \

@@ -46,6 +46,7 @@ struct BoxRec {
   const double* k0h;     // k = 0 pencil in real space: h[n] = sum_m G(0, kz_m) cos(2 pi m n/M)
   const void* twx;       // x twiddles w_Nx^m, m < Nx, plan precision (fused passes A and C)
   const void* twy;       // stage-major y twiddles of Ny (fused passes A and C of groups mixing Ny)
+  const void* twz;       // stage-major z twiddles of M (fused pass B of groups mixing M)
 };
 
 // Pointers held in the records and launch arguments address device global memory.  Kernels
@@ -101,6 +102,9 @@ bool fused_ok(const BoxGeom& g);
 int fused_ac_tiles(int prec, const BoxGeom& g, int variant);
 int fused_b_tiles(const BoxGeom& g);
 int fused_a(const BoxGeom& g);
+// float pass B groups that mix M (padding 2, M <= 256): items of one box per block, 0 if the box
+// cannot join such a group
+int fused_b_items_per_block(const BoxGeom& g, int pad);
 hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
 

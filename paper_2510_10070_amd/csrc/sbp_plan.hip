@@ -413,6 +413,25 @@ void build_launches(sbp_plan p) {
         std::sort(merged.begin(), merged.end());
       }
     }
+    if (kind == sbp::kFB && p->prec == SBP_FP32 && !p->nomix) {
+      // float pass B with padding 2 and M <= 256: groups of different M share one launch
+      // (k_fb_multi, len = 0), rather than one launch each whose blocks all start together
+      std::vector<std::tuple<int, int, int, int, int>> keys;
+      for (auto& kv : groups) {
+        const auto& [len, var, q, a, lin] = kv.first;
+        bool ok = len > 0;
+        for (int b : kv.second) ok = ok && sbp::fused_b_items_per_block(p->boxes[b].g, p->boxes[b].pad) > 0;
+        if (ok) keys.push_back(kv.first);
+      }
+      if (keys.size() >= 2) {
+        std::vector<int>& merged = groups[std::make_tuple(0, 0, 2, 0, 0)];
+        for (const auto& key : keys) {
+          merged.insert(merged.end(), groups[key].begin(), groups[key].end());
+          groups.erase(key);
+        }
+        std::sort(merged.begin(), merged.end());
+      }
+    }
     for (auto& kv : groups) {
       Launch l;
       l.kind = kind;
@@ -425,7 +444,10 @@ void build_launches(sbp_plan p) {
       int acc = 0;
       p->ints.push_back(0);
       for (int b : kv.second) {
-        acc += tiles_of(p->prec, kind, p->boxes[b].g, l.variant);
+        const sbp::BoxGeom& g = p->boxes[b].g;
+        // a pass-B group mixing M: a block takes items_per_block items of its box
+        acc += (kind == sbp::kFB && l.len == 0) ? sbp::fused_b_tiles(g) / sbp::fused_b_items_per_block(g, p->boxes[b].pad)
+                                                 : tiles_of(p->prec, kind, g, l.variant);
         p->ints.push_back(acc);
       }
       l.blocks = acc;
@@ -900,6 +922,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       rec.k0h = (const double*)(p->d_tables + bi.k0h);
       rec.twx = p->d_tables + bi.tw_x;
       rec.twy = p->d_tables + bi.tws_y;
+      rec.twz = p->d_tables + bi.tws_m;
       for (int k = 0; k < 3; ++k) rec.zt64[k] = (const double*)(p->d_tables + bi.zt64[k]);
     }
 

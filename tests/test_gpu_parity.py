@@ -257,6 +257,37 @@ def test_mixed_ny_launch_groups_fp32(remap):
             assert per_mode_error(g, ref) <= TOL["fp32"], b
 
 
+@pytest.mark.parametrize("remap", ["spectral", "linear"])
+def test_mixed_m_launch_groups_fp32(remap):
+    # FP32 pass B runs boxes of different padded length M <= 256 (padding 2) in one launch, every
+    # block taking its box's M and z twiddles from the record; where an item needs fewer than four
+    # wavefronts (M <= 128) a block holds several items of its box, the k = 0 item among them in
+    # the box's first block.  A box with padding 4 keeps a launch of its own.
+    shapes = [(16, 16, 16, 2), (32, 32, 32, 2), (64, 16, 64, 2), (32, 96, 96, 2), (16, 32, 128, 2),
+              (128, 128, 64, 2), (256, 16, 16, 2), (32, 16, 32, 4), (96, 32, 32, 2)]
+    boxes = [dict(_box((nx, ny, nz, 1.0 + 0.1 * i, 1.0 + 0.05 * i, 0.8 + 0.1 * i, pad, 0.0),
+                       "sasha" if i % 3 == 1 else "vgf"), remap=remap)
+             for i, (nx, ny, nz, pad) in enumerate(shapes)]
+    from paper_2510_10070_amd import Box, Plan
+
+    plan = Plan([Box(**b) for b in boxes], precision="fp32", schedule="fused")
+    d = plan.describe()
+    plan.close()
+    assert d["path"] == "fused-3pass", d
+    fb = sorted((g["len"], g["boxes"]) for g in d["groups"] if g["pass"] == "fused_b")
+    assert fb == [(0, 8), (128, 1)], d  # one launch for every M of padding 2, one for the P = 4 box
+    rhos = [lognormal_density(s[:3], 1.0, 0.2, seed=160 + i) for i, s in enumerate(shapes)]
+    shears = [(1.5, 1.0, 0.25 + 0.1 * i, 1.0) for i in range(len(shapes))]
+    for graph in (False, True):
+        got, used = gpu_solve(boxes, rhos, shears, "fp32", schedule="fused", graph=graph)
+        for b, g, u, s in zip(boxes, got, used, shears):
+            ref = oracle_solve(b, u, s)
+            err, pm = rel_l2(g, ref), per_mode_error(g, ref)
+            print(f"{b['nx']}x{b['ny']}x{b['nz']} P{b['pad']} {b['method']} graph={graph}: {err:.2e} {pm:.2e}")
+            assert err <= TOL["fp32"], b
+            assert pm <= TOL["fp32"], b
+
+
 # shapes inside the fused three-pass domain: x split A = nx/16 in {1, 2, 4, 6, 8, 16}, y up to
 # 512, padded z from 32 to 512 and 192, P in {2, 4}; float boxes with nx <= 128 and ny <= 256 take
 # 64-byte rows (16 z cells), so nz = 8 leaves a ragged tile
