@@ -469,8 +469,12 @@ struct WaveSync {
 // reads `buf`; DST_LDS: dst writes `buf`.  Barriers separate every read of `buf` from the
 // next write to it.  On return without DST_LDS the last stage has read `buf`: the caller must
 // barrier before writing it again; with DST_LDS the caller must barrier before reading it.
+// Sy0 is the barrier after stage 0's exchange write.  Stage 0 uses no twiddles, so where the
+// twiddle table in LDS was written by other wavefronts of the block and nothing has synchronised
+// the block since, a wavefront-owned transform (Sy = WaveSync) passes Sy0 = BlockSync: the first
+// twiddle read then follows every wavefront's table writes.
 template <typename T, int N, class RL, class L, int NT, int D, bool SRC_LDS, bool DST_LDS, int S = 0, int Q = 1,
-          class Sy = BlockSync, class TW, class Src, class Dst>
+          class Sy = BlockSync, class Sy0 = Sy, class TW, class Src, class Dst>
 __device__ __forceinline__ void fft_run(cplx<T>* buf, TW tw, int tid, Src&& src, Dst&& dst) {
   using St = Stage<T, N, RL, S, L, NT, D>;
   constexpr bool LAST = S == RL::n - 1;
@@ -488,7 +492,10 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, TW tw, int tid, Src&& src,
     St::template write_fn<(St::R % Q == 0) ? St::R / Q : St::R>(v, tid, dst);
   } else {
     St::write_lds(v, buf, tid);
-    Sy::sync();
+    if constexpr (S == 0)
+      Sy0::sync();
+    else
+      Sy::sync();
     fft_run<T, N, RL, L, NT, D, SRC_LDS, DST_LDS, S + 1, Q, Sy>(buf, tw, tid, src, dst);
   }
 }

@@ -137,22 +137,28 @@ __device__ __forceinline__ void fa_body(const BoxRec* br, int t, const cplx<T>* 
     constexpr bool lin = LIN;  // linear remap (one instantiation each: the spectral path keeps its registers)
     YInterp yi;
     if (lin) yi.init(-br->shy * (x + 0.5), NY);
-    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(
-        mytile, TwS<T>{tw}, stid,
-        [&](int e, int c) {
-          cplx<T> v = mk<T>(T(0), T(0));
-          if (2 * c < zn) {
-            auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * c); };
-            v = lin ? yi.sample<T>(e, NY, ld) : ld(e);
-            if (sasha) {
-              const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
-              s0 += (double)v.x + (double)v.y;
-              s1 += za * (double)v.x + (za + dz) * (double)v.y;
-            }
-          }
-          return v;
-        },
-        [&](int e, int c, cplx<T> v) { mytile[L::at(e, c)] = v; });
+    auto ld_plane = [&](int e, int c) {
+      cplx<T> v = mk<T>(T(0), T(0));
+      if (2 * c < zn) {
+        auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * c); };
+        v = lin ? yi.sample<T>(e, NY, ld) : ld(e);
+        if (sasha) {
+          const double za = -0.5 * g.lz + (z0 + 2 * c + 0.5) * dz;
+          s0 += (double)v.x + (double)v.y;
+          s1 += za * (double)v.x + (za + dz) * (double)v.y;
+        }
+      }
+      return v;
+    };
+    auto st_tile = [&](int e, int c, cplx<T> v) { mytile[L::at(e, c)] = v; };
+    // the twiddle table was written by every wavefront of the block: the first planes' transforms
+    // pass a workgroup barrier before their first twiddle read
+    if (a0 == 0)
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy, BlockSync>(mytile, TwS<T>{tw}, stid,
+                                                                                          ld_plane, st_tile);
+    else
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(mytile, TwS<T>{tw}, stid, ld_plane,
+                                                                             st_tile);
     __syncthreads();
     // every thread collects its positions of all PG planes: separate, remap, keep in registers
 #pragma unroll
@@ -557,22 +563,28 @@ __global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __
     gmem<const T>* src = rho + (size_t)x * NY * nz + z0;
     YInterp yi;
     if (LIN) yi.init(-br->shy * (x + 0.5), NY);
-    fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(
-        mytile, TwS<T>{tw}, stid,
-        [&](int e, int cc) {
-          cplx<T> v = mk<T>(T(0), T(0));
-          if (2 * cc < zn) {
-            auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * cc); };
-            v = LIN ? yi.sample<T>(e, NY, ld) : ld(e);
-            if (sasha) {
-              const double za = -0.5 * g.lz + (z0 + 2 * cc + 0.5) * dz;
-              s0 += (double)v.x + (double)v.y;
-              s1 += za * (double)v.x + (za + dz) * (double)v.y;
-            }
-          }
-          return v;
-        },
-        [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; });
+    auto ld_plane = [&](int e, int cc) {
+      cplx<T> v = mk<T>(T(0), T(0));
+      if (2 * cc < zn) {
+        auto ld = [&](int y) { return *reinterpret_cast<gmem<const cplx<T>>*>(src + (size_t)y * nz + 2 * cc); };
+        v = LIN ? yi.sample<T>(e, NY, ld) : ld(e);
+        if (sasha) {
+          const double za = -0.5 * g.lz + (z0 + 2 * cc + 0.5) * dz;
+          s0 += (double)v.x + (double)v.y;
+          s1 += za * (double)v.x + (za + dz) * (double)v.y;
+        }
+      }
+      return v;
+    };
+    auto st_tile = [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; };
+    // the twiddle table was written by every wavefront of the block: the first planes' transforms
+    // pass a workgroup barrier before their first twiddle read
+    if (a0 == 0)
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy, BlockSync>(mytile, TwS<T>{tw}, stid,
+                                                                                          ld_plane, st_tile);
+    else
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(mytile, TwS<T>{tw}, stid, ld_plane,
+                                                                             st_tile);
     __syncthreads();
     // each lane separates its column of its position from the Hermitian pair and remaps it
 #pragma unroll
