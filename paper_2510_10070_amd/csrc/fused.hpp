@@ -242,7 +242,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fa(GroupArgs ga, const BoxRec* __r
   __shared__ double red[2 * (S::NT / 64)];
   lds_poison(tile, tw, red);
   int t;
-  const BoxRec* br = group_box(ga, recs, t);
+  const BoxRec rec = first_pass_rec(ga, recs, t);
+  const BoxRec* br = &rec;
   fa_body<T, NY, A, B, V, LIN>(br, t, twy, twx, tile, tw, red);
 }
 
@@ -533,7 +534,8 @@ __global__ __launch_bounds__(kFusedAC) void k_fas(GroupArgs ga, const BoxRec* __
   lds_poison(tile, tw, red);
 
   int t;
-  const BoxRec* br = group_box(ga, recs, t);
+  const BoxRec rec = first_pass_rec(ga, recs, t);
+  const BoxRec* br = &rec;
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
   const int sub = tid / TNT, stid = tid - sub * TNT;

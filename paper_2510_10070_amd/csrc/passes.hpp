@@ -120,6 +120,17 @@ __device__ __forceinline__ const BoxRec* group_box(const GroupArgs& ga, const Bo
   return recs + e.x;
 }
 
+// The record of this block's box for the first pass of a solve, as a value: from the launch
+// arguments (block 0 publishing it to the device array for the later passes) or from that array.
+__device__ __forceinline__ BoxRec first_pass_rec(const GroupArgs& ga, const BoxRec* __restrict__ recs, int& tile) {
+  if (ga.use_arg) {
+    tile = xcd_tile(blockIdx.x, ga.total);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *hbm(ga.pub) = ga.arg;
+    return ga.arg;
+  }
+  return *hbm(group_box(ga, recs, tile));
+}
+
 // remap phase exp(-i 2 pi c) for c = my*(2x+1)*fy cycles, evaluated in double
 __device__ __forceinline__ void remap_phase(int my, int x, double fy, double& cs, double& sn) {
   const double c = static_cast<double>(my * (2 * x + 1)) * fy;
@@ -176,7 +187,8 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
   lds_poison(tile, tw, ph, red);
 
   int t;
-  const BoxRec* br = group_box(ga, recs, t);
+  const BoxRec rec = first_pass_rec(ga, recs, t);
+  const BoxRec* br = &rec;
   const BoxGeom g = br->g;
   const int tid = threadIdx.x;
   const int nz = g.nz;

@@ -69,6 +69,12 @@ struct GroupArgs {
   int total;           // = starts[n], the launch's block count
   int box0;            // = box_ids[0]: a one-box group needs no table lookup
   const int2* blk;     // n > 1: (box id, tile) of every block b < total, so one load finds both
+  // Direct launches of a one-box plan: the solve's first pass receives the record with its own
+  // launch (use_arg = 1) rather than from the device array, and its block 0 stores it to `pub`
+  // for the later passes, so no separate record copy runs before it.
+  int use_arg = 0;
+  BoxRec* pub = nullptr;
+  BoxRec arg{};
 };
 
 // Supported transform lengths (x, y and padded z).

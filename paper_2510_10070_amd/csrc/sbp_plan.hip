@@ -484,10 +484,17 @@ void build_launches(sbp_plan p) {
   }
 }
 
-hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
+// arg: the solve's record for a one-box group that is the solve's first launch (direct launches),
+// handed to the kernel with the launch
+hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st, const sbp::BoxRec* arg = nullptr) {
   const char* T = p->d_tables;
   sbp::GroupArgs ga{p->d_ints + l.ints_off, p->d_ints + l.ints_off + l.n, l.n, l.blocks, p->ints[l.ints_off],
                     l.n > 1 ? p->d_blk + l.blk_off : nullptr};
+  if (arg) {
+    ga.use_arg = 1;
+    ga.pub = p->d_recs + ga.box0;
+    ga.arg = *arg;
+  }
   switch (l.kind) {
     case sbp::kYFwd:
       return sbp::launch_y(p->prec, true, true, l.len, l.variant, ga, l.blocks, p->d_recs, T + l.tw, st);
@@ -510,11 +517,18 @@ hipError_t launch_one(sbp_plan p, const Launch& l, hipStream_t st) {
 // fetch_slot < 0, from the slot named by the device-side ring counter (graph capture).
 sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot, const sbp::BoxRec* arg_recs = nullptr) {
   const char* T = p->d_tables;
-  if (mk) mk->mark("records");
-  if (arg_recs)
-    HIP_TRY(sbp::launch_fetch_args(arg_recs, p->d_recs, (int)p->nrec, st));
-  else
-    HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
+  // a one-box plan whose first launch is its box's first pass (fused pass A or the forward y
+  // pass) hands the record to that launch
+  const bool inline_rec = arg_recs && !(p->flags & SBP_FLAG_PLAIN) && p->nrec == 1 && !p->launches.empty() &&
+                          (p->launches[0].kind == sbp::kFA || p->launches[0].kind == sbp::kYFwd) &&
+                          p->launches[0].n == 1;
+  if (!inline_rec) {
+    if (mk) mk->mark("records");
+    if (arg_recs)
+      HIP_TRY(sbp::launch_fetch_args(arg_recs, p->d_recs, (int)p->nrec, st));
+    else
+      HIP_TRY(sbp::launch_fetch(p->d_stage, p->d_recs, (int)p->nrec, p->nslots, fetch_slot, p->d_ctl, st));
+  }
   if (p->flags & SBP_FLAG_PLAIN) {
     const BoxInfo& bi = p->boxes[0];
     sbp::GroupArgs one{p->d_ints, p->d_ints + 1, 1, 0, 0, nullptr};
@@ -522,9 +536,10 @@ sbp_status enqueue(sbp_plan p, hipStream_t st, Marker* mk, int fetch_slot, const
                               T + bi.tws_x, T + bi.tws_y, T + bi.tw_m, st, mk ? mark_cb : nullptr, mk));
     return SBP_OK;
   }
-  for (const Launch& l : p->launches) {
+  for (size_t i = 0; i < p->launches.size(); ++i) {
+    const Launch& l = p->launches[i];
     if (mk) mk->mark(kPassName[l.kind]);  // kinds stay distinct in the timing records
-    HIP_TRY(launch_one(p, l, st));
+    HIP_TRY(launch_one(p, l, st, (i == 0 && inline_rec) ? arg_recs : nullptr));
   }
   if (mk) mk->mark(nullptr);
   return SBP_OK;
