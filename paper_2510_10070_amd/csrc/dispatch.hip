@@ -41,6 +41,7 @@ int fused_ac_tiles(int prec, const BoxGeom& g, int variant) {
 }
 int fused_b_tiles(const BoxGeom& g) { return (g.nx / kFusedB16) * (g.ny / 2); }
 int fused_a(const BoxGeom& g) { return g.nx / kFusedB16; }
+int fused_ac_multi_tiles(const BoxGeom& g) { return fused_ac_multi_tiles_t<float>(g); }
 int fused_b_items_per_block(const BoxGeom& g, int pad) {
   if (pad != 2 || g.m > kMultiMMax) return 0;
   const int ipb = fb_multi_items_per_block(g.m);

@@ -16,8 +16,12 @@ namespace sbp {
 
 constexpr int kFusedAC = 512;  // threads of passes A and C
 
-// real z cells per pass-A/C tile: variant 0 = 32-byte rows, 1 = 64-byte rows, 2 = 16-byte rows
-template <typename T, int V> constexpr int fa_zc() { return (V == 1 ? 64 : V == 2 ? 16 : 32) / (int)sizeof(T); }
+// real z cells per pass-A/C tile: variant 0 = 32-byte rows, 1 = 64-byte rows, 2 = 16-byte rows;
+// kWideRows = 128-byte rows, taken only by the launches that mix Ny, for Ny <= 64
+constexpr int kWideRows = 4;
+template <typename T, int V> constexpr int fa_zc() {
+  return (V == kWideRows ? 128 : V == 1 ? 64 : V == 2 ? 16 : 32) / (int)sizeof(T);
+}
 // threads per pass-A/C block: variant 2 tiles are half as wide and take half the threads, so
 // that two blocks fit on a CU at the register count of pass C
 template <int V> constexpr int fa_threads() { return V == 2 ? kFusedAC / 2 : kFusedAC; }
@@ -48,7 +52,8 @@ template <typename T, int NY, int A, int V, bool C> struct AcShape {
   static constexpr int NB = fa_zc<T, V>() / 2;
   static constexpr int NT = fa_threads<V>();
   // pass C with 32-byte rows and Ny <= 256: eight planes at a time, one wavefront per plane
-  static constexpr int PG = C ? fa_pg<A, ((V == 0 || V == 1) && NY <= 256) ? 8 : 4>() : fa_pg<A, V == 1 ? 8 : 4>();
+  static constexpr int PG = C ? fa_pg<A, ((V == 0 || V == 1 || V == kWideRows) && NY <= 256) ? 8 : 4>()
+                               : fa_pg<A, (V == 1 || V == kWideRows) ? 8 : 4>();
   static constexpr int TILE = PG * pad_slots<PAD>(NY * NB);  // PG plane tiles
 };
 // the largest tile over A in {1, 2, 4, 6, 8} (launch groups that mix Nx)
@@ -455,54 +460,64 @@ __global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec*
   fc_mix_body<T, NY, B, V, LIN>(br, t, twy, tile, tw);
 }
 
-// Passes A and C for a launch group whose boxes differ in Ny <= 128 as well as in A <= 8 (float,
-// 64-byte rows): every block runs the body of its own box's Ny and A with that box's y and x
-// twiddles, so the groups of a batch that would each be one launch per Ny share one, and their
-// blocks fill the chip together.  Registers and LDS are those of the largest body (Ny = 128).
+// Passes A and C for a launch group whose boxes differ in Ny <= 128 as well as in A <= 8 (float):
+// every block runs the body of its own box's Ny and A with that box's y and x twiddles, so the
+// groups of a batch that would each be one launch per Ny share one, and their blocks fill the chip
+// together.  Boxes of Ny = 96 and 128 take 64-byte rows; boxes of Ny <= 64 take 128-byte rows, so
+// that a block holds as many (y, z) positions per plane as one of Ny = 128 (the same LDS tile and
+// registers, twice the loads in flight per lane and half the blocks of 64-byte rows).  Registers
+// and LDS are those of the largest body.
 constexpr int kMultiNyMax = 128;
-template <typename T, int V, bool C> constexpr int ac_multi_tile() {
-  constexpr int t[5] = {ac_mix_tile<T, 16, V, C>(), ac_mix_tile<T, 32, V, C>(), ac_mix_tile<T, 64, V, C>(),
-                        ac_mix_tile<T, 96, V, C>(), ac_mix_tile<T, 128, V, C>()};
+template <int NY> constexpr int multi_rows() { return NY <= 64 ? kWideRows : 1; }
+template <typename T, bool C> constexpr int ac_multi_tile() {
+  constexpr int t[5] = {ac_mix_tile<T, 16, multi_rows<16>(), C>(), ac_mix_tile<T, 32, multi_rows<32>(), C>(),
+                        ac_mix_tile<T, 64, multi_rows<64>(), C>(), ac_mix_tile<T, 96, multi_rows<96>(), C>(),
+                        ac_mix_tile<T, 128, multi_rows<128>(), C>()};
   int m = 0;
   for (int v : t) m = v > m ? v : m;
   return m;
 }
+// tiles of one box in such a launch (host side)
+template <typename T> int fused_ac_multi_tiles_t(const BoxGeom& g) {
+  const int zc = g.ny <= 64 ? fa_zc<T, kWideRows>() : fa_zc<T, 1>();
+  return kFusedB16 * ((g.nz + zc - 1) / zc);
+}
 
-template <typename T, int B, int V, bool LIN>
+template <typename T, int B, bool LIN>
 __global__ __launch_bounds__(kFusedAC) void k_fa_multi(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                        const cplx<T>* __restrict__, const cplx<T>* __restrict__) {
-  constexpr int NT = fa_threads<V>();
-  __shared__ cplx<T> tile[ac_multi_tile<T, V, false>()];
+  static_assert(fa_threads<1>() == kFusedAC && fa_threads<kWideRows>() == kFusedAC, "one block size");
+  __shared__ cplx<T> tile[ac_multi_tile<T, false>()];
   __shared__ cplx<T> tw[kMultiNyMax];
-  __shared__ double red[2 * (NT / 64)];
+  __shared__ double red[2 * (kFusedAC / 64)];
   lds_poison(tile, tw, red);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
   switch (br->g.ny) {
-    case 16: fa_mix_body<T, 16, B, V, LIN>(br, t, twy, tile, tw, red); break;
-    case 32: fa_mix_body<T, 32, B, V, LIN>(br, t, twy, tile, tw, red); break;
-    case 64: fa_mix_body<T, 64, B, V, LIN>(br, t, twy, tile, tw, red); break;
-    case 96: fa_mix_body<T, 96, B, V, LIN>(br, t, twy, tile, tw, red); break;
-    default: fa_mix_body<T, 128, B, V, LIN>(br, t, twy, tile, tw, red); break;
+    case 16: fa_mix_body<T, 16, B, multi_rows<16>(), LIN>(br, t, twy, tile, tw, red); break;
+    case 32: fa_mix_body<T, 32, B, multi_rows<32>(), LIN>(br, t, twy, tile, tw, red); break;
+    case 64: fa_mix_body<T, 64, B, multi_rows<64>(), LIN>(br, t, twy, tile, tw, red); break;
+    case 96: fa_mix_body<T, 96, B, multi_rows<96>(), LIN>(br, t, twy, tile, tw, red); break;
+    default: fa_mix_body<T, 128, B, multi_rows<128>(), LIN>(br, t, twy, tile, tw, red); break;
   }
 }
 
-template <typename T, int B, int V, bool LIN>
+template <typename T, int B, bool LIN>
 __global__ __launch_bounds__(kFusedAC) void k_fc_multi(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                        const cplx<T>* __restrict__, const cplx<T>* __restrict__) {
-  __shared__ cplx<T> tile[ac_multi_tile<T, V, true>()];
+  __shared__ cplx<T> tile[ac_multi_tile<T, true>()];
   __shared__ cplx<T> tw[kMultiNyMax];
   lds_poison(tile, tw);
   int t;
   const BoxRec* br = group_box(ga, recs, t);
   const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
   switch (br->g.ny) {
-    case 16: fc_mix_body<T, 16, B, V, LIN>(br, t, twy, tile, tw); break;
-    case 32: fc_mix_body<T, 32, B, V, LIN>(br, t, twy, tile, tw); break;
-    case 64: fc_mix_body<T, 64, B, V, LIN>(br, t, twy, tile, tw); break;
-    case 96: fc_mix_body<T, 96, B, V, LIN>(br, t, twy, tile, tw); break;
-    default: fc_mix_body<T, 128, B, V, LIN>(br, t, twy, tile, tw); break;
+    case 16: fc_mix_body<T, 16, B, multi_rows<16>(), LIN>(br, t, twy, tile, tw); break;
+    case 32: fc_mix_body<T, 32, B, multi_rows<32>(), LIN>(br, t, twy, tile, tw); break;
+    case 64: fc_mix_body<T, 64, B, multi_rows<64>(), LIN>(br, t, twy, tile, tw); break;
+    case 96: fc_mix_body<T, 96, B, multi_rows<96>(), LIN>(br, t, twy, tile, tw); break;
+    default: fc_mix_body<T, 128, B, multi_rows<128>(), LIN>(br, t, twy, tile, tw); break;
   }
 }
 

@@ -97,8 +97,8 @@ SBP_FUSED_NY(SBP_EXTERN_AC_D)
 #undef SBP_EXTERN_AC_F
 #undef SBP_EXTERN_AC_D
 
-// passes A (kind 0) and C (kind 2) for a group that mixes Ny <= 128 and A <= 8 (float, variant 1;
-// instantiated in fused_f32_multi.hip)
+// passes A (kind 0) and C (kind 2) for a group that mixes Ny <= 128 and A <= 8 (float, variant 1
+// boxes, run in 64- or 128-byte rows by Ny; instantiated in fused_f32_multi.hip)
 template <typename T>
 hipError_t launch_ac_multi(int kind, bool lin, GroupArgs ga, int blocks, const BoxRec* recs, hipStream_t st);
 extern template hipError_t launch_ac_multi<float>(int, bool, GroupArgs, int, const BoxRec*, hipStream_t);
@@ -110,11 +110,11 @@ hipError_t launch_ac_multi(int kind, bool lin, GroupArgs ga, int blocks, const B
     const dim3 grid(blocks), block(fa_threads<1>());
     const cplx<T>* none = nullptr;
     if (kind == 0) {
-      if (lin) hipLaunchKernelGGL((k_fa_multi<T, B, 1, true>), grid, block, 0, st, ga, recs, none, none);
-      else hipLaunchKernelGGL((k_fa_multi<T, B, 1, false>), grid, block, 0, st, ga, recs, none, none);
+      if (lin) hipLaunchKernelGGL((k_fa_multi<T, B, true>), grid, block, 0, st, ga, recs, none, none);
+      else hipLaunchKernelGGL((k_fa_multi<T, B, false>), grid, block, 0, st, ga, recs, none, none);
     } else {
-      if (lin) hipLaunchKernelGGL((k_fc_multi<T, B, 1, true>), grid, block, 0, st, ga, recs, none, none);
-      else hipLaunchKernelGGL((k_fc_multi<T, B, 1, false>), grid, block, 0, st, ga, recs, none, none);
+      if (lin) hipLaunchKernelGGL((k_fc_multi<T, B, true>), grid, block, 0, st, ga, recs, none, none);
+      else hipLaunchKernelGGL((k_fc_multi<T, B, false>), grid, block, 0, st, ga, recs, none, none);
     }
     return hipGetLastError();
   } else {

@@ -111,6 +111,8 @@ int fused_a(const BoxGeom& g);
 // float pass B groups that mix M (padding 2, M <= 256): items of one box per block, 0 if the box
 // cannot join such a group
 int fused_b_items_per_block(const BoxGeom& g, int pad);
+// float pass A/C groups that mix Ny: tiles of one box (rows of 64 or 128 bytes by Ny)
+int fused_ac_multi_tiles(const BoxGeom& g);
 hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st);
 

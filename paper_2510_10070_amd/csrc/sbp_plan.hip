@@ -445,9 +445,16 @@ void build_launches(sbp_plan p) {
       p->ints.push_back(0);
       for (int b : kv.second) {
         const sbp::BoxGeom& g = p->boxes[b].g;
-        // a pass-B group mixing M: a block takes items_per_block items of its box
-        acc += (kind == sbp::kFB && l.len == 0) ? sbp::fused_b_tiles(g) / sbp::fused_b_items_per_block(g, p->boxes[b].pad)
-                                                 : tiles_of(p->prec, kind, g, l.variant);
+        int nt;
+        if (kind == sbp::kFB && l.len == 0)  // a block takes items_per_block items of its box
+          nt = sbp::fused_b_tiles(g) / sbp::fused_b_items_per_block(g, p->boxes[b].pad);
+        else if ((kind == sbp::kFA || kind == sbp::kFC) && l.len == 0)  // rows by Ny
+          nt = sbp::fused_ac_multi_tiles(g);
+        else
+          nt = tiles_of(p->prec, kind, g, l.variant);
+        // each tile of the first pass writes one SASHA partial-sum pair
+        if (kind == sbp::kFA || kind == sbp::kYFwd) p->boxes[b].first_tiles = nt;
+        acc += nt;
         p->ints.push_back(acc);
       }
       l.blocks = acc;
@@ -970,12 +977,13 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       sbp_status us = upload_groups(p.get());
       if (us != SBP_OK) return us;
     }
-    // partial-sum slots used by the chosen y variant
+    // partial-sum slots written by the first pass as launched (its tiles)
     for (size_t r = 0; r < p->nrec; ++r) {
       const BoxInfo& bi = p->boxes[(flags & SBP_FLAG_PLAIN) ? 0 : r];
-      p->master[r].npartials = (flags & SBP_FLAG_PLAIN) ? sbp::kPlainPartials
-                               : bi.fused ? sbp::fused_ac_tiles(prec, bi.g, bi.var[sbp::kFA])
-                                          : sbp::y_tiles(prec, bi.g, bi.var[sbp::kYFwd]);
+      if (!(flags & SBP_FLAG_PLAIN) && (bi.first_tiles <= 0 || bi.first_tiles > bi.npartials))
+        return fail(SBP_E_STATE, "box %zu: %d first-pass tiles for %d partial-sum slots", r, bi.first_tiles,
+                    bi.npartials);
+      p->master[r].npartials = (flags & SBP_FLAG_PLAIN) ? sbp::kPlainPartials : bi.first_tiles;
     }
     *out = p.release();
     return SBP_OK;

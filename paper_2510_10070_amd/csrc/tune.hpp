@@ -36,7 +36,8 @@ struct BoxInfo {
   size_t ws_off = 0;   // half spectrum (plain: padded spectrum)
   size_t ws2_off = 0;  // plain: unpadded half spectrum
   size_t part_off = 0;
-  int npartials = 0;
+  int npartials = 0;    // partial-sum slots reserved (every tiling the plan may launch)
+  int first_tiles = 0;  // tiles of the first pass as launched (set with the launch groups)
   size_t data_bytes = 0;
   int var[kKinds] = {1, 1, 1, 1, 1, 0, 0, 0};  // tile variant per pass kind
   int var_src[kKinds] = {0, 0, 0, 0, 0, 0, 0, 0};  // where var[k] came from: kVarSrc*

@@ -258,6 +258,36 @@ def test_mixed_ny_launch_groups_fp32(remap):
 
 
 @pytest.mark.parametrize("remap", ["spectral", "linear"])
+def test_mixed_ny_wide_rows_fp32(remap):
+    # in a launch that mixes Ny, boxes of Ny <= 64 take 128-byte rows (32 z cells per tile): z
+    # lengths that fill one tile, several tiles, and ragged last tiles (nz = 8, 48, 96), with the
+    # SASHA partial sums of the wider tiles and P = 4 boxes among them
+    shapes = [(64, 64, 48, 4), (32, 32, 8, 4), (128, 16, 96, 2), (16, 64, 128, 2), (96, 128, 32, 2),
+              (64, 96, 64, 2), (32, 32, 32, 2), (128, 64, 16, 2)]
+    boxes = [dict(_box((nx, ny, nz, 1.0 + 0.1 * i, 0.9 + 0.05 * i, 1.0, pad, 0.0),
+                       "sasha" if i % 2 else "vgf"), remap=remap)
+             for i, (nx, ny, nz, pad) in enumerate(shapes)]
+    from paper_2510_10070_amd import Box, Plan
+
+    plan = Plan([Box(**b) for b in boxes], precision="fp32", schedule="fused")
+    d = plan.describe()
+    plan.close()
+    assert d["path"] == "fused-3pass", d
+    assert sorted((g["pass"], g["len"]) for g in d["groups"] if g["pass"] != "fused_b") == \
+        [("fused_a", 0), ("fused_c", 0)], d  # passes A and C: one launch each
+    rhos = [lognormal_density(s[:3], 1.0, 0.2, seed=180 + i) for i, s in enumerate(shapes)]
+    shears = [(1.5, 1.0, 0.35 + 0.1 * i, 1.0) for i in range(len(shapes))]
+    for graph in (False, True):
+        got, used = gpu_solve(boxes, rhos, shears, "fp32", schedule="fused", graph=graph)
+        for b, g, u, s in zip(boxes, got, used, shears):
+            ref = oracle_solve(b, u, s)
+            err, pm = rel_l2(g, ref), per_mode_error(g, ref)
+            print(f"{b['nx']}x{b['ny']}x{b['nz']} P{b['pad']} {b['method']} graph={graph}: {err:.2e} {pm:.2e}")
+            assert err <= TOL["fp32"], b
+            assert pm <= TOL["fp32"], b
+
+
+@pytest.mark.parametrize("remap", ["spectral", "linear"])
 def test_mixed_m_launch_groups_fp32(remap):
     # FP32 pass B runs boxes of different padded length M <= 256 (padding 2) in one launch, every
     # block taking its box's M and z twiddles from the record; where an item needs fewer than four
