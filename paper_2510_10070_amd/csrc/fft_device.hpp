@@ -242,6 +242,19 @@ template <> struct Inv<768> { using L = RList<3, 4, 8, 8>; };
 template <> struct Fwd<1024> { using L = RList<8, 8, 4, 4>; };
 template <> struct Inv<1024> { using L = RList<4, 4, 8, 8>; };
 
+// Radix schedules of the padded z transforms (forward F, inverse I), which run forward and back
+// with the hand-off in registers (fft_fwd_op_inv): those of Fwd and Inv, except where a palindrome
+// lets one stage-major table serve both directions, so that a lane can keep its twiddles in
+// registers for every pencil it transforms (TwReg).
+template <int N> struct ZSched {
+  using F = typename Fwd<N>::L;
+  using I = typename Inv<N>::L;
+};
+template <> struct ZSched<256> {
+  using F = RList<8, 4, 8>;
+  using I = RList<8, 4, 8>;
+};
+
 // Tile layout: NB transforms, element (j, b) at logical index j*LD + b*BS, LDS slot
 // pad_map<PAD>(.) (PAD 0: pad8).  BFAST selects which index consecutive threads walk (batch index
 // for z-fastest tiles, element index otherwise), so that neighbouring lanes touch neighbouring
@@ -348,7 +361,7 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
             if constexpr (std::is_pointer_v<TW>)
               t = tw[k * r * (N / (NS * R))];
             else if constexpr (TW::kInRegisters)
-              t = tw.template stage<S, NS>(r, k);
+              t = tw.template stage<S, NS>(p, r, k);
             else
               t = tw.at(NS - 1 + (r - 1) * NS + k);
             v[p][r] = D < 0 ? cmul<T>(v[p][r], t) : cmulc<T>(v[p][r], t);
@@ -417,32 +430,37 @@ template <typename T, int N, class RL, int S, class L, int NT, int D> struct Sta
   }
 };
 
-// The twiddles one thread needs, held in registers: for a schedule RL whose stages give every
-// thread one butterfly (PER == 1), the thread's twiddle index k of each stage is fixed, so the
-// R - 1 twiddles of stages FIRST.. can be fetched once from the stage-major table `src` and reused
-// by every transform the thread runs with that schedule; earlier stages still read `src`.  An
-// inverse transform may use the same object when its schedule equals RL (the stages conjugate).
+// The twiddles one thread needs, held in registers: the butterflies a thread runs in each stage
+// (PER of them) are the same for every transform of schedule RL it runs, so their twiddle
+// indices k are fixed, and the R - 1 twiddles of each butterfly of stages FIRST.. can be fetched
+// once from the stage-major table `src` and reused; earlier stages still read `src`.  (Where two
+// butterflies of a thread share k, the two fetches read one address.)  An inverse transform may
+// use the same object when its schedule equals RL (the stages conjugate).
 template <typename T, int N, class RL, class L, int NT, class SRC, int FIRST = 1> struct TwReg {
   static constexpr bool kInRegisters = true;
+  static constexpr int kPerMax = 2;
   SRC src;
-  cplx<T> w[RL::n][8];
+  cplx<T> w[RL::n][kPerMax][8];
   __device__ __forceinline__ void load(int tid) { load_stage<FIRST>(tid); }
   template <int S> __device__ __forceinline__ void load_stage(int tid) {
     if constexpr (S < RL::n) {
       using St = Stage<T, N, RL, S, L, NT, -1>;
-      static_assert(St::PER == 1, "one butterfly per thread and stage");
+      static_assert(St::PER <= kPerMax, "butterflies per thread and stage above the register table");
       static_assert(St::R <= 8, "radix above the register table");
-      int j, b;
-      St::item(tid, 0, j, b);
-      const int k = j % St::NS;
 #pragma unroll
-      for (int r = 1; r < St::R; ++r) w[S][r] = src.at(St::NS - 1 + (r - 1) * St::NS + k);
+      for (int p = 0; p < St::PER; ++p) {
+        int j, b;
+        St::item(tid, p, j, b);
+        const int k = j % St::NS;
+#pragma unroll
+        for (int r = 1; r < St::R; ++r) w[S][p][r] = src.at(St::NS - 1 + (r - 1) * St::NS + k);
+      }
       load_stage<S + 1>(tid);
     }
   }
-  template <int S, int NS> __device__ __forceinline__ cplx<T> stage(int r, int k) const {
+  template <int S, int NS> __device__ __forceinline__ cplx<T> stage(int p, int r, int k) const {
     if constexpr (S >= FIRST)
-      return w[S][r];
+      return w[S][p][r];
     else
       return src.at(NS - 1 + (r - 1) * NS + k);
   }
@@ -501,7 +519,7 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, TW tw, int tid, Src&& src,
 }
 
 // Forward transform, pointwise op, inverse transform, with the hand-off between the last
-// forward stage and the first inverse stage kept in registers.
+// forward stage and the first inverse stage kept in registers (the z schedules ZSched<N>).
 //   src(elem, b) -> cplx (forward inputs), op(elem, b, cplx&) on spectrum values (op(elem, b,
 //   cplx&, slot) also gets the register slot, which is fixed per thread and element, see
 //   spectrum_slot), dst(elem, b, v) (inverse outputs); twf, twi: twiddles of the forward and of the inverse
@@ -513,14 +531,14 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, TW tw, int tid, Src&& src,
 // same on every call, so per-element constants can be fetched once per thread.
 template <typename T, int N, class L, int NT>
 __device__ __forceinline__ int spectrum_slot(int tid, int i) {
-  using RF = typename Fwd<N>::L;
+  using RF = typename ZSched<N>::F;
   using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
   int j, b;
   if (!Sf::item(tid, i / Sf::R, j, b)) return -1;
   return j + (i % Sf::R) * Sf::NBF;
 }
 template <typename T, int N, class L, int NT> constexpr int spectrum_slots() {
-  using RF = typename Fwd<N>::L;
+  using RF = typename ZSched<N>::F;
   using Sf = Stage<T, N, RF, RF::n - 1, L, NT, -1>;
   return Sf::PER * Sf::R;
 }
@@ -529,8 +547,8 @@ template <typename T, int N, class L, int NT, int S, int Q = 1, class Sy = Block
           class Src, class Op, class Dst>
 __device__ __forceinline__ void fft_fwd_op_inv(cplx<T>* buf, TWF twf, TWI twi, int tid, Src&& src, Op&& op,
                                                Dst&& dst) {
-  using RF = typename Fwd<N>::L;
-  using RI = typename Inv<N>::L;
+  using RF = typename ZSched<N>::F;
+  using RI = typename ZSched<N>::I;
   static_assert(RF::r[RF::n - 1] == RI::r[0], "hand-off needs matching radices");
   if constexpr (S < RF::n - 1) {
     // forward stages before the last one

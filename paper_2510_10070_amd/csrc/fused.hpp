@@ -792,15 +792,26 @@ template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves
 // there (TwH), which keeps pass B's LDS small enough for four blocks per CU in float (M = 512 in
 // float needs neither: its twiddles live in registers, below).
 template <int M, int B, int Q> constexpr bool fb_tw_in_holes() {
-  return same_schedule<typename Fwd<M>::L, typename Inv<M>::L>() && B * (M / Q) >= 8 * (M - 1) + 8;
+  return same_schedule<typename ZSched<M>::F, typename ZSched<M>::I>() && B * (M / Q) >= 8 * (M - 1) + 8;
 }
-// Float plans whose schedule gives each lane one butterfly per stage keep the lane's twiddles in
-// registers, read once per block from the table in HBM: pass B is bound by LDS issue, and those
-// reads would be the same for every pencil.  The hint asks for at least three waves per SIMD
-// (the M = 512 kernel fits four).
+// butterflies per lane in every stage of schedule RL for PW pencils of length M over 64 lanes
+template <class RL, int M, int PW> constexpr int fb_max_per() {
+  int m = 0;
+  for (int s = 0; s < RL::n; ++s) {
+    const int per = ((M / RL::r[s]) * PW + 63) / 64;
+    m = per > m ? per : m;
+  }
+  return m;
+}
+// Float plans whose z schedule gives each lane one butterfly in the first stage and at most two
+// in the others keep the lane's twiddles in registers, read once per block from the table in
+// HBM: pass B is bound by LDS issue, and those reads would be the same for every pencil.  The
+// hint asks for at least three waves per SIMD (the M = 512 kernel fits four).
 template <typename T, int M, int B, int Q> constexpr bool fb_tw_in_registers() {
-  using S0 = Stage<T, M, typename Fwd<M>::L, 0, Tile<fb_pw<M, B, Q>(), 1, M, false>, 64, -1>;
-  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && S0::PER == 1;
+  using RL = typename ZSched<M>::F;
+  using S0 = Stage<T, M, RL, 0, Tile<fb_pw<M, B, Q>(), 1, M, false>, 64, -1>;
+  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && S0::PER == 1 &&
+         fb_max_per<RL, M, fb_pw<M, B, Q>()>() <= 2;
 }
 template <typename T, int M, int B, int Q> constexpr int fb_waves_per_eu() {
   if constexpr (fb_tw_in_registers<T, M, B, Q>())
@@ -813,7 +824,7 @@ template <typename T, int M, int B, int Q> struct FbShared {
   static constexpr int PW = fb_pw<M, B, Q>();
   static constexpr int NZ = M / Q;
   static constexpr bool kF32 = std::is_same<T, float>::value;
-  static constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
+  static constexpr bool kOneTw = same_schedule<typename ZSched<M>::F, typename ZSched<M>::I>();
   // register twiddles (read once from HBM): the tile needs no twiddle slots, and at M = 512 it
   // takes the padding with fewer bank conflicts in the 8.8.8 exchanges
   static constexpr bool kTwReg = fb_tw_in_registers<T, M, B, Q>();
@@ -937,8 +948,8 @@ __device__ __forceinline__ void fb_pencils(FbShared<T, M, B, Q>& sh, const FbIte
   constexpr int PAD = FbShared<T, M, B, Q>::PAD;
   using LT = Tile<B, 1, NZ, false, PAD>;
   using LW = Tile<PW, 1, M, false, PAD>;  // one group's exchange layout inside its tuple's tile area
-  using RF = typename Fwd<M>::L;
-  using RI = typename Inv<M>::L;
+  using RF = typename ZSched<M>::F;
+  using RI = typename ZSched<M>::I;
   using S0 = Stage<T, M, RF, 0, LW, 64, -1>;
   using SL = Stage<T, M, RI, RI::n - 1, LW, 64, +1>;
   constexpr int RIN = (S0::R % Q == 0) ? S0::R / Q : S0::R;

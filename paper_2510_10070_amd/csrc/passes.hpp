@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   __shared__ cplx<T> xbuf[WV * XS];
   lds_poison(xbuf);
   // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
-  constexpr bool kOneTw = same_schedule<typename Fwd<M>::L, typename Inv<M>::L>();
+  constexpr bool kOneTw = same_schedule<typename ZSched<M>::F, typename ZSched<M>::I>();
   __shared__ cplx<T> tw[kOneTw ? M : 2 * M];
   __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW], psp[WV][PPW];
   lds_poison(tw, pa0, pe, pik, pk2, psp);

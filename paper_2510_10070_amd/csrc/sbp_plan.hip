@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -201,15 +202,21 @@ void stage_major(int n, const std::vector<long double>& re, const std::vector<lo
   }
 }
 
-// the forward schedule's table of length n, then the inverse schedule's
-bool stage_major_pair(int n, const std::vector<long double>& re, const std::vector<long double>& im,
+// the forward schedule's table of length n, then the inverse schedule's (z: the schedules of the
+// padded z transforms, ZSched)
+bool stage_major_pair(int n, bool z, const std::vector<long double>& re, const std::vector<long double>& im,
                       std::vector<long double>& ore, std::vector<long double>& oim) {
   std::vector<long double> fr, fi, ir, ii;
   bool ok = false;
 #define SBP_CASE(N_)                                                 \
   if (n == N_) {                                                     \
-    stage_major<typename sbp::Fwd<N_>::L>(n, re, im, fr, fi);        \
-    stage_major<typename sbp::Inv<N_>::L>(n, re, im, ir, ii);        \
+    if (z) {                                                         \
+      stage_major<typename sbp::ZSched<N_>::F>(n, re, im, fr, fi);   \
+      stage_major<typename sbp::ZSched<N_>::I>(n, re, im, ir, ii);   \
+    } else {                                                         \
+      stage_major<typename sbp::Fwd<N_>::L>(n, re, im, fr, fi);      \
+      stage_major<typename sbp::Inv<N_>::L>(n, re, im, ir, ii);      \
+    }                                                                \
     ok = true;                                                       \
   }
   SBP_FOR_EACH_LEN(SBP_CASE)
@@ -225,7 +232,7 @@ bool stage_major_pair(int n, const std::vector<long double>& re, const std::vect
 struct TableBuilder {
   std::vector<char> host;
   std::map<std::pair<int, int>, size_t> tw;  // (n, prec) -> offset
-  std::map<std::pair<int, int>, size_t> tws;  // (n, prec) -> offset of the stage-major pair
+  std::map<std::tuple<int, int, bool>, size_t> tws;  // (n, prec, z) -> offset of the stage-major pair
   size_t put(const void* p, size_t bytes) {
     size_t off = align_up(host.size());
     host.resize(off + bytes);
@@ -259,14 +266,15 @@ struct TableBuilder {
     }
     return put(v.data(), v.size() * sizeof(T));
   }
-  // stage-major twiddles of length n: 2n entries, forward schedule then inverse schedule
-  size_t stage_twiddles(int n, int prec) {
-    auto key = std::make_pair(n, prec);
+  // stage-major twiddles of length n: 2n entries, forward schedule then inverse schedule (z: the
+  // schedules of the padded z transforms)
+  size_t stage_twiddles(int n, int prec, bool z = false) {
+    auto key = std::make_tuple(n, prec, z);
     auto it = tws.find(key);
     if (it != tws.end()) return it->second;
     std::vector<long double> re, im, sre, sim;
     twiddles(n, re, im);
-    stage_major_pair(n, re, im, sre, sim);  // n is a validated length
+    stage_major_pair(n, z, re, im, sre, sim);  // n is a validated length
     const size_t off = prec ? put_cplx<float>(sre, sim) : put_cplx<double>(sre, sim);
     tws[key] = off;
     return off;
@@ -834,7 +842,7 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       bi.tw_m64 = tb.twiddle(pad * b.nz, 0);
       bi.tws_x = tb.stage_twiddles(b.nx, prec);
       bi.tws_y = tb.stage_twiddles(b.ny, prec);
-      bi.tws_m = tb.stage_twiddles(pad * b.nz, prec);
+      bi.tws_m = tb.stage_twiddles(pad * b.nz, prec, true);
       std::vector<long double> s2, ks, kz2;
       ztables(bi.g, pad, s2, ks, kz2);
       bi.zt64[0] = put_vec<double>(tb, s2);
