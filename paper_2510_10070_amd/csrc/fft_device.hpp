@@ -250,6 +250,14 @@ template <int N> struct ZSched {
   using F = typename Fwd<N>::L;
   using I = typename Inv<N>::L;
 };
+template <> struct ZSched<128> {
+  using F = RList<4, 8, 4>;
+  using I = RList<4, 8, 4>;
+};
+template <> struct ZSched<192> {
+  using F = RList<8, 3, 8>;
+  using I = RList<8, 3, 8>;
+};
 template <> struct ZSched<256> {
   using F = RList<8, 4, 8>;
   using I = RList<8, 4, 8>;

@@ -803,15 +803,13 @@ template <class RL, int M, int PW> constexpr int fb_max_per() {
   }
   return m;
 }
-// Float plans whose z schedule gives each lane one butterfly in the first stage and at most two
-// in the others keep the lane's twiddles in registers, read once per block from the table in
-// HBM: pass B is bound by LDS issue, and those reads would be the same for every pencil.  The
-// hint asks for at least three waves per SIMD (the M = 512 kernel fits four).
+// Float plans whose z schedule gives each lane at most two butterflies per stage keep the lane's
+// twiddles in registers, read once per block from the table in HBM: pass B is bound by LDS
+// issue, and those reads would be the same for every pencil.  The hint asks for at least three
+// waves per SIMD (the M = 512 kernel fits four).
 template <typename T, int M, int B, int Q> constexpr bool fb_tw_in_registers() {
   using RL = typename ZSched<M>::F;
-  using S0 = Stage<T, M, RL, 0, Tile<fb_pw<M, B, Q>(), 1, M, false>, 64, -1>;
-  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && S0::PER == 1 &&
-         fb_max_per<RL, M, fb_pw<M, B, Q>()>() <= 2;
+  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && fb_max_per<RL, M, fb_pw<M, B, Q>()>() <= 2;
 }
 template <typename T, int M, int B, int Q> constexpr int fb_waves_per_eu() {
   if constexpr (fb_tw_in_registers<T, M, B, Q>())
