@@ -474,6 +474,17 @@ template <typename T, int N, class RL, class L, int NT, class SRC, int FIRST = 1
   }
 };
 
+// the most butterflies a lane runs in one stage of schedule RL, for PW transforms of length N over
+// 64 lanes (TwReg holds up to two per stage)
+template <class RL, int N, int PW> constexpr int max_per() {
+  int m = 0;
+  for (int s = 0; s < RL::n; ++s) {
+    const int per = ((N / RL::r[s]) * PW + 63) / 64;
+    m = per > m ? per : m;
+  }
+  return m;
+}
+
 // Barrier policies of the engine.  BlockSync: the tile is shared by the whole workgroup.
 // WaveSync: the tile belongs to one wavefront; its LDS operations complete in issue order, so
 // only the compiler must be kept from moving accesses across the exchange point.

@@ -794,22 +794,13 @@ template <int M, int B, int Q> constexpr int fb_threads() { return 64 * fb_waves
 template <int M, int B, int Q> constexpr bool fb_tw_in_holes() {
   return same_schedule<typename ZSched<M>::F, typename ZSched<M>::I>() && B * (M / Q) >= 8 * (M - 1) + 8;
 }
-// butterflies per lane in every stage of schedule RL for PW pencils of length M over 64 lanes
-template <class RL, int M, int PW> constexpr int fb_max_per() {
-  int m = 0;
-  for (int s = 0; s < RL::n; ++s) {
-    const int per = ((M / RL::r[s]) * PW + 63) / 64;
-    m = per > m ? per : m;
-  }
-  return m;
-}
 // Float plans whose z schedule gives each lane at most two butterflies per stage keep the lane's
 // twiddles in registers, read once per block from the table in HBM: pass B is bound by LDS
 // issue, and those reads would be the same for every pencil.  The hint asks for at least three
 // waves per SIMD (the M = 512 kernel fits four).
 template <typename T, int M, int B, int Q> constexpr bool fb_tw_in_registers() {
   using RL = typename ZSched<M>::F;
-  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && fb_max_per<RL, M, fb_pw<M, B, Q>()>() <= 2;
+  return std::is_same<T, float>::value && fb_tw_in_holes<M, B, Q>() && max_per<RL, M, fb_pw<M, B, Q>()>() <= 2;
 }
 template <typename T, int M, int B, int Q> constexpr int fb_waves_per_eu() {
   if constexpr (fb_tw_in_registers<T, M, B, Q>())

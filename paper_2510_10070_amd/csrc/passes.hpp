@@ -451,9 +451,12 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   constexpr int XS = pad_slots<PAD>(PW * M);
   __shared__ cplx<T> xbuf[WV * XS];
   lds_poison(xbuf);
-  // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs
+  // stage-major twiddles of the forward schedule of M, then of the inverse one if it differs; in
+  // float, where one table serves both and a lane runs at most two butterflies per stage, each
+  // lane keeps its own twiddles in registers (read once from HBM) instead
   constexpr bool kOneTw = same_schedule<typename ZSched<M>::F, typename ZSched<M>::I>();
-  __shared__ cplx<T> tw[kOneTw ? M : 2 * M];
+  constexpr bool kTwReg = kF32 && kOneTw && max_per<typename ZSched<M>::F, M, PW>() <= 2;
+  __shared__ cplx<T> tw[kTwReg ? 1 : kOneTw ? M : 2 * M];
   __shared__ T pa0[WV][PPW], pe[WV][PPW], pik[WV][PPW], pk2[WV][PPW], psp[WV][PPW];
   lds_poison(tw, pa0, pe, pik, pk2, psp);
   // block-0 work before the wavefront transforms borrows xbuf (SASHA reduction, then the double
@@ -475,7 +478,9 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   gmem<const T>* zt = hbm(static_cast<const T*>(br->zt));
   const int pw0 = (t * WV + wave) * PPW;  // first pencil of this wavefront
 
-  load_twiddles<T, kOneTw ? M : 2 * M, NT>(tw, twg, tid);
+  if constexpr (!kTwReg) load_twiddles<T, kOneTw ? M : 2 * M, NT>(tw, twg, tid);
+  TwReg<T, M, typename ZSched<M>::F, LW, 64, TwS<T>> twr{TwS<T>{twg}};
+  if constexpr (kTwReg) twr.load(lane);
   if (lane < PPW) {
     const int q = min(pw0 + lane, np - 1);
     const int mx = q / hy, my = q - mx * hy;
@@ -567,7 +572,8 @@ __global__ __launch_bounds__(kPassThreads) void k_z(GroupArgs ga, const BoxRec* 
   for (int g0 = 0; g0 < PPW; g0 += PW) {
     if (pw0 + g0 >= np) break;  // uniform across the wavefront
     fft_fwd_op_inv<T, M, LW, 64, 0, Q, WaveSync>(
-        xw, TwS<T>{tw}, TwS<T>{tw + (kOneTw ? 0 : M)}, lane,
+        xw, [&] { if constexpr (kTwReg) return twr; else return TwS<T>{tw}; }(),
+        [&] { if constexpr (kTwReg) return twr; else return TwS<T>{tw + (kOneTw ? 0 : M)}; }(), lane,
         [&](int e, int p) {
           const int q = pw0 + g0 + p;
           return (e < nz && q < np && !(own0 && q == 0)) ? W[(size_t)q * nz + e] : mk<T>(T(0), T(0));
