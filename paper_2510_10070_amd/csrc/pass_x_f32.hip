@@ -7,11 +7,11 @@ template <>
 hipError_t launch_x_impl<float>(int dir, int nx, int variant, GroupArgs ga, int blocks, const BoxRec* recs,
                              const void* tw, hipStream_t st) {
   using T = float;
-  const dim3 grid(blocks), block(kPassThreads);
+  const dim3 grid(blocks);
   const cplx<T>* t = static_cast<const cplx<T>*>(tw);
 #define SBP_LAUNCH(N_, V_)                                                                     \
-  if (dir < 0) hipLaunchKernelGGL((k_x<T, N_, V_, -1>), grid, block, 0, st, ga, recs, t);      \
-  else hipLaunchKernelGGL((k_x<T, N_, V_, +1>), grid, block, 0, st, ga, recs, t);
+  if (dir < 0) hipLaunchKernelGGL((k_x<T, N_, V_, -1>), grid, dim3(xy_threads<N_>()), 0, st, ga, recs, t);      \
+  else hipLaunchKernelGGL((k_x<T, N_, V_, +1>), grid, dim3(xy_threads<N_>()), 0, st, ga, recs, t);
 #define SBP_CASE(N_)                  \
   if (nx == N_) {                     \
     if (variant) { SBP_LAUNCH(N_, 1) } \

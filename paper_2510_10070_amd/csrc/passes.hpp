@@ -81,6 +81,9 @@ __device__ __forceinline__ T green_at_nonzero(T a0, T e, T ik, T k2, const ZRow<
 }
 
 constexpr int kPassThreads = 256;
+// threads of an x or y pass block: transforms of 512 points or more take 512 threads, so that the
+// two or three blocks that fit a CU in LDS bring twice the wavefronts to its FFT stages
+template <int N> constexpr int xy_threads() { return N >= 512 ? 512 : kPassThreads; }
 
 // ------------------------------------------------------------------------------------------
 // tile shapes per (precision, transform length, variant)
@@ -173,11 +176,11 @@ struct YInterp {
 // and stored for my < Ny/2 (the Nyquist row is dropped).  SASHA: double partial sums.
 
 template <typename T, int NY, int V, bool REMAP>
-__global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRec* __restrict__ recs,
+__global__ __launch_bounds__(xy_threads<NY>()) void k_yfwd(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                        const cplx<T>* __restrict__ twg) {
   constexpr int ZC = y_zc<T, NY, V>();
   constexpr int NB = ZC / 2;
-  constexpr int NT = kPassThreads;
+  constexpr int NT = xy_threads<NY>();
   constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
   using L = Tile<NB, NB, 1, true, PAD>;
   __shared__ cplx<T> tile[pad_slots<PAD>(NY * NB)];
@@ -284,11 +287,11 @@ __global__ __launch_bounds__(kPassThreads) void k_yfwd(GroupArgs ga, const BoxRe
 // as one complex signal, one inverse FFT, real/imaginary parts written as z and z+1, plus
 // Phi_0(z) for SASHA.
 template <typename T, int NY, int V, bool REMAP>
-__global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRec* __restrict__ recs,
+__global__ __launch_bounds__(xy_threads<NY>()) void k_yinv(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                        const cplx<T>* __restrict__ twg) {
   constexpr int ZC = y_zc<T, NY, V>();
   constexpr int NB = ZC / 2;
-  constexpr int NT = kPassThreads;
+  constexpr int NT = xy_threads<NY>();
   constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
   using L = Tile<NB, NB, 1, true, PAD>;
   __shared__ cplx<T> tile[pad_slots<PAD>(NY * NB)];
@@ -390,10 +393,10 @@ __global__ __launch_bounds__(kPassThreads) void k_yinv(GroupArgs ga, const BoxRe
 // x: one block per (my, chunk of ZC consecutive z cells); rows of ZC contiguous complex values.
 
 template <typename T, int NX, int V, int D>
-__global__ __launch_bounds__(kPassThreads) void k_x(GroupArgs ga, const BoxRec* __restrict__ recs,
+__global__ __launch_bounds__(xy_threads<NX>()) void k_x(GroupArgs ga, const BoxRec* __restrict__ recs,
                                                     const cplx<T>* __restrict__ twg) {
   constexpr int ZC = x_zc<T, NX, V>();
-  constexpr int NT = kPassThreads;
+  constexpr int NT = xy_threads<NX>();
   constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
   using L = Tile<ZC, ZC, 1, true, PAD>;
   __shared__ cplx<T> buf[pad_slots<PAD>(NX * ZC)];
