@@ -463,24 +463,59 @@ __global__ __launch_bounds__(kFusedAC) void k_fc_mix(GroupArgs ga, const BoxRec*
 // Passes A and C for a launch group whose boxes differ in Ny <= 128 as well as in A <= 8 (float):
 // every block runs the body of its own box's Ny and A with that box's y and x twiddles, so the
 // groups of a batch that would each be one launch per Ny share one, and their blocks fill the chip
-// together.  Boxes of Ny = 96 and 128 take 64-byte rows; boxes of Ny <= 64 take 128-byte rows, so
-// that a block holds as many (y, z) positions per plane as one of Ny = 128 (the same LDS tile and
-// registers, twice the loads in flight per lane and half the blocks of 64-byte rows).  Registers
-// and LDS are those of the largest body.
+// together.  Boxes of Ny <= 64, and boxes of A <= 4, take 128-byte rows, the others 64-byte rows,
+// so that a block holds about as many (y, z) positions times planes as one of Ny = 128 and A = 8
+// (the same LDS tile and registers, twice the loads in flight per lane and half the blocks of
+// 64-byte rows).  Registers and LDS are those of the largest body.
 constexpr int kMultiNyMax = 128;
-template <int NY> constexpr int multi_rows() { return NY <= 64 ? kWideRows : 1; }
+// row width in such a launch: 128-byte rows where Ny <= 64 or A <= 4, which keeps a thread's
+// positions times planes (and the plane tiles of a block) within those of Ny = 128 and A = 8 in
+// 64-byte rows
+constexpr int multi_rows(int ny, int a) { return (ny <= 64 || a <= 4) ? kWideRows : 1; }
+template <typename T, int NY, bool C> constexpr int ac_multi_ny_tile() {
+  constexpr int t[5] = {AcShape<T, NY, 1, multi_rows(NY, 1), C>::TILE, AcShape<T, NY, 2, multi_rows(NY, 2), C>::TILE,
+                        AcShape<T, NY, 4, multi_rows(NY, 4), C>::TILE, AcShape<T, NY, 6, multi_rows(NY, 6), C>::TILE,
+                        AcShape<T, NY, 8, multi_rows(NY, 8), C>::TILE};
+  int m = 0;
+  for (int v : t) m = v > m ? v : m;
+  return m;
+}
 template <typename T, bool C> constexpr int ac_multi_tile() {
-  constexpr int t[5] = {ac_mix_tile<T, 16, multi_rows<16>(), C>(), ac_mix_tile<T, 32, multi_rows<32>(), C>(),
-                        ac_mix_tile<T, 64, multi_rows<64>(), C>(), ac_mix_tile<T, 96, multi_rows<96>(), C>(),
-                        ac_mix_tile<T, 128, multi_rows<128>(), C>()};
+  constexpr int t[5] = {ac_multi_ny_tile<T, 16, C>(), ac_multi_ny_tile<T, 32, C>(), ac_multi_ny_tile<T, 64, C>(),
+                        ac_multi_ny_tile<T, 96, C>(), ac_multi_ny_tile<T, 128, C>()};
   int m = 0;
   for (int v : t) m = v > m ? v : m;
   return m;
 }
 // tiles of one box in such a launch (host side)
 template <typename T> int fused_ac_multi_tiles_t(const BoxGeom& g) {
-  const int zc = g.ny <= 64 ? fa_zc<T, kWideRows>() : fa_zc<T, 1>();
+  const int zc = multi_rows(g.ny, g.nx / kFusedB16) == kWideRows ? fa_zc<T, kWideRows>() : fa_zc<T, 1>();
   return kFusedB16 * ((g.nz + zc - 1) / zc);
+}
+// the bodies of a block's box: its Ny (template) and A, with that box's x twiddles
+template <typename T, int NY, int B, bool LIN>
+__device__ __forceinline__ void fa_multi_body(const BoxRec* br, int t, const cplx<T>* __restrict__ twy, cplx<T>* tile,
+                                              cplx<T>* tw, double* red) {
+  const cplx<T>* twx = static_cast<const cplx<T>*>(br->twx);
+  switch (br->g.nx / B) {
+    case 1: fa_body<T, NY, 1, B, multi_rows(NY, 1), LIN>(br, t, twy, twx, tile, tw, red); break;
+    case 2: fa_body<T, NY, 2, B, multi_rows(NY, 2), LIN>(br, t, twy, twx, tile, tw, red); break;
+    case 4: fa_body<T, NY, 4, B, multi_rows(NY, 4), LIN>(br, t, twy, twx, tile, tw, red); break;
+    case 6: fa_body<T, NY, 6, B, multi_rows(NY, 6), LIN>(br, t, twy, twx, tile, tw, red); break;
+    default: fa_body<T, NY, 8, B, multi_rows(NY, 8), LIN>(br, t, twy, twx, tile, tw, red); break;
+  }
+}
+template <typename T, int NY, int B, bool LIN>
+__device__ __forceinline__ void fc_multi_body(const BoxRec* br, int t, const cplx<T>* __restrict__ twy, cplx<T>* tile,
+                                              cplx<T>* tw) {
+  const cplx<T>* twx = static_cast<const cplx<T>*>(br->twx);
+  switch (br->g.nx / B) {
+    case 1: fc_body<T, NY, 1, B, multi_rows(NY, 1), LIN>(br, t, twy, twx, tile, tw); break;
+    case 2: fc_body<T, NY, 2, B, multi_rows(NY, 2), LIN>(br, t, twy, twx, tile, tw); break;
+    case 4: fc_body<T, NY, 4, B, multi_rows(NY, 4), LIN>(br, t, twy, twx, tile, tw); break;
+    case 6: fc_body<T, NY, 6, B, multi_rows(NY, 6), LIN>(br, t, twy, twx, tile, tw); break;
+    default: fc_body<T, NY, 8, B, multi_rows(NY, 8), LIN>(br, t, twy, twx, tile, tw); break;
+  }
 }
 
 template <typename T, int B, bool LIN>
@@ -495,11 +530,11 @@ __global__ __launch_bounds__(kFusedAC) void k_fa_multi(GroupArgs ga, const BoxRe
   const BoxRec* br = group_box(ga, recs, t);
   const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
   switch (br->g.ny) {
-    case 16: fa_mix_body<T, 16, B, multi_rows<16>(), LIN>(br, t, twy, tile, tw, red); break;
-    case 32: fa_mix_body<T, 32, B, multi_rows<32>(), LIN>(br, t, twy, tile, tw, red); break;
-    case 64: fa_mix_body<T, 64, B, multi_rows<64>(), LIN>(br, t, twy, tile, tw, red); break;
-    case 96: fa_mix_body<T, 96, B, multi_rows<96>(), LIN>(br, t, twy, tile, tw, red); break;
-    default: fa_mix_body<T, 128, B, multi_rows<128>(), LIN>(br, t, twy, tile, tw, red); break;
+    case 16: fa_multi_body<T, 16, B, LIN>(br, t, twy, tile, tw, red); break;
+    case 32: fa_multi_body<T, 32, B, LIN>(br, t, twy, tile, tw, red); break;
+    case 64: fa_multi_body<T, 64, B, LIN>(br, t, twy, tile, tw, red); break;
+    case 96: fa_multi_body<T, 96, B, LIN>(br, t, twy, tile, tw, red); break;
+    default: fa_multi_body<T, 128, B, LIN>(br, t, twy, tile, tw, red); break;
   }
 }
 
@@ -513,11 +548,11 @@ __global__ __launch_bounds__(kFusedAC) void k_fc_multi(GroupArgs ga, const BoxRe
   const BoxRec* br = group_box(ga, recs, t);
   const cplx<T>* twy = static_cast<const cplx<T>*>(br->twy);
   switch (br->g.ny) {
-    case 16: fc_mix_body<T, 16, B, multi_rows<16>(), LIN>(br, t, twy, tile, tw); break;
-    case 32: fc_mix_body<T, 32, B, multi_rows<32>(), LIN>(br, t, twy, tile, tw); break;
-    case 64: fc_mix_body<T, 64, B, multi_rows<64>(), LIN>(br, t, twy, tile, tw); break;
-    case 96: fc_mix_body<T, 96, B, multi_rows<96>(), LIN>(br, t, twy, tile, tw); break;
-    default: fc_mix_body<T, 128, B, multi_rows<128>(), LIN>(br, t, twy, tile, tw); break;
+    case 16: fc_multi_body<T, 16, B, LIN>(br, t, twy, tile, tw); break;
+    case 32: fc_multi_body<T, 32, B, LIN>(br, t, twy, tile, tw); break;
+    case 64: fc_multi_body<T, 64, B, LIN>(br, t, twy, tile, tw); break;
+    case 96: fc_multi_body<T, 96, B, LIN>(br, t, twy, tile, tw); break;
+    default: fc_multi_body<T, 128, B, LIN>(br, t, twy, tile, tw); break;
   }
 }
 

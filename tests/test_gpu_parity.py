@@ -259,11 +259,12 @@ def test_mixed_ny_launch_groups_fp32(remap):
 
 @pytest.mark.parametrize("remap", ["spectral", "linear"])
 def test_mixed_ny_wide_rows_fp32(remap):
-    # in a launch that mixes Ny, boxes of Ny <= 64 take 128-byte rows (32 z cells per tile): z
-    # lengths that fill one tile, several tiles, and ragged last tiles (nz = 8, 48, 96), with the
-    # SASHA partial sums of the wider tiles and P = 4 boxes among them
+    # in a launch that mixes Ny, boxes of Ny <= 64 or A <= 4 take 128-byte rows (32 z cells per
+    # tile), the others 64-byte rows: z lengths that fill one tile, several tiles, and ragged last
+    # tiles (nz = 8, 48, 96), with the SASHA partial sums of the wider tiles and P = 4 boxes
     shapes = [(64, 64, 48, 4), (32, 32, 8, 4), (128, 16, 96, 2), (16, 64, 128, 2), (96, 128, 32, 2),
-              (64, 96, 64, 2), (32, 32, 32, 2), (128, 64, 16, 2)]
+              (64, 96, 64, 2), (32, 32, 32, 2), (128, 64, 16, 2), (64, 128, 48, 4), (32, 96, 96, 2),
+              (128, 128, 64, 2)]
     boxes = [dict(_box((nx, ny, nz, 1.0 + 0.1 * i, 0.9 + 0.05 * i, 1.0, pad, 0.0),
                        "sasha" if i % 2 else "vgf"), remap=remap)
              for i, (nx, ny, nz, pad) in enumerate(shapes)]
