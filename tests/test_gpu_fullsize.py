@@ -13,6 +13,8 @@ benchmark uses.
       sheared horizontal modes, so these profiles do not depend on Nx, Ny);
     - on the clumpy density itself, properties that hold at any size: y-translation
       equivariance and linearity.
+* 1024 x 1024 x 512 (the largest box the ABI accepts, M = 1024), FP32 and FP64: the sheared-wave
+  check at sampled points.
 """
 
 import math
@@ -197,4 +199,42 @@ def test_clumpy_1024_translation_and_linearity():
     print(f"clumpy-1024 fp32: translation {e_roll:.3e}, linearity {e_lin:.3e}")
     assert e_roll <= TOL["fp32"], e_roll
     assert e_lin <= TOL["fp32"], e_lin
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_largest_box_sampled_against_oracle_profiles(precision):
+    # the largest box the ABI accepts, 1024 x 1024 x 512 (M = 1024, five-pass): a sheared wave of
+    # mode numbers (5, 7) at full size, sampled against the z profiles the oracle computes on a
+    # 16 x 16 horizontal grid of the same box (the operator is diagonal in the sheared modes)
+    import torch
+
+    from paper_2510_10070_amd import Box, Plan, Shear
+
+    b = (1024, 1024, 512, 16.0, 16.0, 4.0)
+    shear = (1.5, 1.0, 5.0, 1.0)
+    nx, ny, nz = b[:3]
+    small = 16
+    rho_s, th1_s, th2_s = _sheared_wave(small, small, b, shear, mx=5, my=7)
+    phi_s = oracle.solve(rho_s, oracle.Box(small, small, nz, *b[3:]), oracle.Shear(*shear))
+    basis = np.stack([np.cos(th1_s).ravel(), np.cos(th2_s).ravel()], axis=1)
+    prof, *_ = np.linalg.lstsq(basis, phi_s.reshape(small * small, nz), rcond=None)
+    assert np.abs(basis @ prof - phi_s.reshape(small * small, nz)).max() <= 1e-12 * np.abs(phi_s).max()
+
+    rho_f, th1, th2 = _sheared_wave(nx, ny, b, shear, mx=5, my=7)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    plan = Plan(Box(*b), precision=precision)
+    assert plan.describe()["path"] == "streaming-5pass"
+    r = torch.tensor(rho_f, dtype=dt, device="cuda:0")
+    del rho_f
+    phi = torch.empty_like(r)
+    plan.solve(r, phi, Shear(*shear))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    ix, iy, iz = rng.integers(0, nx, 400000), rng.integers(0, ny, 400000), rng.integers(0, nz, 400000)
+    got = phi[torch.as_tensor(ix), torch.as_tensor(iy), torch.as_tensor(iz)].double().cpu().numpy()
+    want = np.cos(th1[ix, iy]) * prof[0, iz] + np.cos(th2[ix, iy]) * prof[1, iz]
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    print(f"1024x1024x512 sheared wave {precision}: sampled rel-L2 {err:.3e}")
+    assert err <= TOL[precision], err
     plan.close()
