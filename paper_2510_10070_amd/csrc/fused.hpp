@@ -17,7 +17,7 @@ namespace sbp {
 constexpr int kFusedAC = 512;  // threads of passes A and C
 
 // real z cells per pass-A/C tile: variant 0 = 32-byte rows, 1 = 64-byte rows, 2 = 16-byte rows;
-// kWideRows = 128-byte rows, taken only by the launches that mix Ny, for Ny <= 64
+// kWideRows = 128-byte rows, taken only by the launches that mix Ny (for Ny <= 64 or A <= 4)
 constexpr int kWideRows = 4;
 template <typename T, int V> constexpr int fa_zc() {
   return (V == kWideRows ? 128 : V == 1 ? 64 : V == 2 ? 16 : 32) / (int)sizeof(T);
