@@ -541,3 +541,27 @@ def test_max_box_count():
         worst = max(worst, rel_l2(g, oracle_solve(b, u, s)))
     print(f"4096 boxes fp32: worst rel-L2 {worst:.3e}")
     assert worst <= TOL["fp32"], worst
+
+
+@pytest.mark.parametrize("shape,pad", [((128, 16, 16), 4), ((128, 32, 32), 2), ((128, 64, 64), 2)],
+                         ids=["128x16x16_P4", "128x32x32_P2", "128x64x64_P2"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_repeated_solves_are_bitwise_identical(shape, pad, precision):
+    # the same solve repeated gives the same bits: boxes whose pass-A y transforms are each owned by
+    # one wavefront (A = 8 planes side by side: 64-byte rows in float, the split kernel in double;
+    # with Ny = 16 the y twiddle table of a block comes from its first wavefront alone), launched
+    # directly and back to back
+    import torch
+
+    from paper_2510_10070_amd import Box, Plan, Shear
+
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    rho = torch.tensor(lognormal_density(shape, 1.0, 0.3, seed=sum(shape) + pad), dtype=dt, device="cuda:0")
+    plan = Plan(Box(*shape, 1.2, 0.9, 1.0, pad=pad), precision=precision, schedule="fused")
+    outs = [torch.empty_like(rho) for _ in range(48)]
+    for o in outs:
+        plan.solve(rho, o, Shear(t=0.41))
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs[1:], 1):
+        assert torch.equal(o, outs[0]), k
+    plan.close()
