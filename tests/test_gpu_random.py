@@ -3,7 +3,8 @@
 Each case draws a box (every axis from the lengths the ABI accepts, kept small enough for the
 oracle), the padding and truncation, the method, the remap, the precision, the shear parameters
 and the launch mode (direct or graph-replayed, fused or five-pass by default); a few cases hold
-several boxes at once.  The draw is fixed (seed below), so a failure names a reproducible case."""
+several boxes at once, and a second draw holds only plans of 2 to 8 boxes.  The draws are fixed
+(seeds below), so a failure names a reproducible case."""
 
 import numpy as np
 import pytest
@@ -61,3 +62,26 @@ def test_random_plan(case):
         err, mp = rel_l2(g, ref), max_pointwise_error(g, ref)
         assert err <= TOL[case["precision"]], (b, s, case["precision"], err)
         assert mp <= TOL[case["precision"]], (b, s, case["precision"], mp)
+
+
+def _batch_cases():
+    # plans of 2 to 8 boxes, mostly float, so that launches mix Nx, Ny and M (the multi-box
+    # kernels, their wide rows and their items per block) across many shapes
+    rng = np.random.default_rng(SEED + 1)
+    out = []
+    for _ in range(60):
+        nbox = int(rng.integers(2, 9))
+        boxes = [_draw_box(rng) for _ in range(nbox)]
+        shears = [(float(rng.choice([1.5, 2.0])), float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.0, 3.0)),
+                   float(rng.uniform(0.2, 2.0))) for _ in range(nbox)]
+        out.append(dict(boxes=boxes, shears=shears, precision=str(rng.choice(["fp32", "fp32", "fp64"])),
+                        graph=bool(rng.random() < 0.3), schedule="auto", seed=int(rng.integers(0, 2**31))))
+    return out
+
+
+BATCH_CASES = _batch_cases()
+
+
+@pytest.mark.parametrize("case", BATCH_CASES, ids=[f"batch{i}" for i in range(len(BATCH_CASES))])
+def test_random_batch_plan(case):
+    test_random_plan(case)
