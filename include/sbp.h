@@ -78,10 +78,13 @@ typedef enum { SBP_REMAP_SPECTRAL = 0, SBP_REMAP_LINEAR = 1 } sbp_remap;
 #define SBP_FLAG_FUSED 0x10u    /* fused three-pass schedule (x split into 16 x nx/16, four-step):
                                    three HBM round trips of the half spectrum.  It applies to
                                    power-of-two 16 <= nx <= 256, 16 <= ny <= 512 and
-                                   32 <= pad*nz <= 512; other boxes of the plan run five-pass.
+                                   32 <= pad*nz <= 512, and, with this flag only, to FP32 boxes
+                                   with nx and ny in {512, 1024}, pad 2 and 64 <= 2*nz <= 512 (x
+                                   split into 64 x nx/64); other boxes of the plan run five-pass.
                                    Without either schedule flag a plan takes the fused schedule
-                                   wherever it applies (the faster on gfx950 in both precisions).
-                                   Both flags together are SBP_E_ARG. */
+                                   wherever it is the faster on gfx950: the narrow boxes above in
+                                   both precisions, not the wide FP32 ones (there five-pass is
+                                   1.2-1.5 x faster).  Both flags together are SBP_E_ARG. */
 
 /* Geometry, method and remap of one box.
  *   nx, ny: horizontal cells, each in {8,12,16,24,32,48,64,96,128,192,256,384,512,768,1024};

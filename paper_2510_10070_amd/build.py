@@ -25,7 +25,7 @@ SOURCES = ["sbp_plan.hip", "tune.hip", "dispatch.hip", "plain.hip", "pass_y_f32.
            "fused_f32.hip", "fused_f64.hip", "gravity.hip"]
 # fused passes A and C, split by Ny so that they compile in parallel
 SOURCES += [f"fused_{p}_{y}.hip" for p in ("f32", "f64") for y in ("y16_64", "y96_128", "y256", "y512")]
-SOURCES += ["fused_f32_multi.hip", "fused_f32_multi_b.hip"]
+SOURCES += ["fused_f32_multi.hip", "fused_f32_multi_b.hip", "fused_f32_wide_ac.hip", "fused_f32_wide_b.hip"]
 # translation units whose host code the sanitizer build instruments
 HOST_SOURCES = ["sbp_plan.hip", "tune.hip", "dispatch.hip", "plain.hip", "gravity.hip"]
 

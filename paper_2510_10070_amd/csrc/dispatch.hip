@@ -1,7 +1,7 @@
 // Precision dispatch of the pass launchers (no kernels are instantiated here).
 #include <cstring>
 
-#include "fused.hpp"
+#include "fused_wide.hpp"
 
 namespace sbp {
 
@@ -35,20 +35,29 @@ hipError_t launch_z(int prec, int m, int variant, int q, GroupArgs ga, int block
 
 namespace sbp {
 
+// fused boxes with Nx > 256 are the wide float boxes (B = 64)
+static int fused_bsize(const BoxGeom& g) { return g.nx > 256 ? kWideB : kFusedB16; }
 bool fused_ok(const BoxGeom& g) { return fused_supported(g.nx, g.ny, g.m); }
+bool fused_wide_ok(int prec, const BoxGeom& g) { return prec == 1 && fused_wide_supported(g.nx, g.ny, g.nz, g.m); }
 int fused_ac_tiles(int prec, const BoxGeom& g, int variant) {
+  if (g.nx > 256) return fused_wide_ac_tiles(g);
   return prec ? fused_ac_tiles_t<float>(g, variant) : fused_ac_tiles_t<double>(g, variant);
 }
-int fused_b_tiles(const BoxGeom& g) { return (g.nx / kFusedB16) * (g.ny / 2); }
-int fused_a(const BoxGeom& g) { return g.nx / kFusedB16; }
+int fused_b_tiles(const BoxGeom& g) { return (g.nx / fused_bsize(g)) * (g.ny / 2); }
+int fused_a(const BoxGeom& g) { return g.nx / fused_bsize(g); }
 int fused_ac_multi_tiles(const BoxGeom& g) { return fused_ac_multi_tiles_t<float>(g); }
 int fused_b_items_per_block(const BoxGeom& g, int pad) {
-  if (pad != 2 || g.m > kMultiMMax) return 0;
+  if (pad != 2 || g.m > kMultiMMax || g.nx > 256) return 0;
   const int ipb = fb_multi_items_per_block(g.m);
   return ipb > 0 && fused_b_tiles(g) % ipb == 0 ? ipb : 0;
 }
 hipError_t launch_fused(int prec, int kind, int len, int a, int variant, int q, bool lin, GroupArgs ga, int blocks,
                         const BoxRec* recs, const void* tw, const void* tw2, hipStream_t st) {
+  if (variant == kWideVariant) {
+    if (prec != 1) return hipErrorInvalidValue;
+    return kind == 1 ? launch_fused_wide_b(len, q, ga, blocks, recs, tw, st)
+                     : launch_fused_wide_ac(kind, len, a, lin, ga, blocks, recs, tw, tw2, st);
+  }
   return prec ? launch_fused_impl<float>(kind, len, a, variant, q, lin, ga, blocks, recs, tw, tw2, st)
               : launch_fused_impl<double>(kind, len, a, variant, q, lin, ga, blocks, recs, tw, tw2, st);
 }

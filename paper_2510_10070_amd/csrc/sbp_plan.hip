@@ -22,6 +22,7 @@
 #include "fft_device.hpp"
 #include "sbp_internal.hpp"
 #include "tune.hpp"
+#include "wide.hpp"
 
 namespace {
 
@@ -878,7 +879,9 @@ sbp_status sbp_plan_create(const sbp_box* boxes, int32_t nbox, int32_t precision
       }
       sbp::default_variants(prec, bi.g, bi.var);
       const bool want_fused = (flags & SBP_FLAG_FUSED) || !(flags & (SBP_FLAG_PLAIN | SBP_FLAG_FIVE_PASS));
-      bi.fused = want_fused && sbp::fused_ok(bi.g);
+      // the wide float boxes run fused on request only: five-pass is faster there (the wide passes
+      // A and C stream 8- or 16-byte z rows with one block per CU)
+      bi.fused = want_fused && (sbp::fused_ok(bi.g) || ((flags & SBP_FLAG_FUSED) && sbp::fused_wide_ok(prec, bi.g)));
       const size_t n = (size_t)b.nx * b.ny * b.nz;
       bi.data_bytes = n * w;
       if (flags & SBP_FLAG_PLAIN) {

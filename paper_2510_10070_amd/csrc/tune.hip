@@ -19,6 +19,7 @@
 #include <tuple>
 
 #include "tune.hpp"
+#include "wide.hpp"
 
 namespace sbp {
 
@@ -37,12 +38,15 @@ void default_variants(int prec, const BoxGeom& g, int var[kKinds]) {
   // five-pass float y transforms longer than 512: half-width rows (1024 x 1024 x 256: 809 -> 552 us
   // forward, 1235 -> 696 us inverse, the autotuner's choice too)
   if (prec && g.ny > 512) var[kYFwd] = var[kYInv] = 0;
+  // fused float boxes wider than 256 cells take the wide schedule (B = 64), one kernel per pass
+  if (prec && g.nx > 256) var[kFA] = var[kFB] = var[kFC] = kWideVariant;
 }
 
 // The fused pass-A/C kernels that exist: variant 0 (32-byte rows) always; variant 1 (64-byte
 // rows) for float with A <= 8 and Ny <= 256; variant 2 (16-byte rows, 256 threads) for pass C
 // with Ny <= 256; variant 3 (the split kernels, one z column per lane) with Ny <= 256.
 bool fused_variant_ok(int prec, int kind, const BoxGeom& g, int v) {
+  if (g.nx > 256) return v == kWideVariant;
   if (kind != kFA && kind != kFC) return v == 0;
   const int a = g.nx / 16;
   switch (v) {
@@ -105,7 +109,7 @@ Key key_of(const std::string& arch, int prec, const BoxInfo& b, int kind) {
 
 // kinds a box's schedule uses that have a choice of variants
 bool tunable(const BoxInfo& b, int kind) {
-  if (b.fused) return kind == kFA || kind == kFC;
+  if (b.fused) return (kind == kFA || kind == kFC) && b.g.nx <= 256;  // the wide schedule has one variant
   return kind < 5;
 }
 
