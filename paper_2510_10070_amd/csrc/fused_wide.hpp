@@ -34,7 +34,8 @@ inline int fused_wide_ac_tiles(const BoxGeom& g) {
 // Pass A: one block per (j, chunk of ZC z cells).  The two real z columns of a position
 // (ky, c) are held by a lane pair, one column per lane, and each lane pair owns POS positions,
 // so that every lane keeps POS x A complex values (at most 16).  PG planes are transformed side
-// by side (four of 256 threads over 16-byte rows, eight of 128 over 8-byte rows).
+// by side (four of 256 threads over 16-byte rows; over 8-byte rows all sixteen, one wavefront
+// each).
 
 template <int NY, int A> struct WideAc {
   static constexpr int ZC = wide_zc(NY, A);
@@ -45,9 +46,13 @@ template <int NY, int A> struct WideAc {
   static constexpr int LP = NT / 2;       // lane pairs
   static_assert(QN % LP == 0, "positions tile the lane pairs");
   static constexpr int POS = QN / LP;
-  static constexpr int PG = NB == 1 ? 8 : 4;  // planes transformed side by side
+  // planes transformed side by side: over 8-byte rows all A = 16 at once, one wavefront each
+  // (no workgroup barrier between the stages of a transform); over 16-byte rows four of 256
+  // threads
+  static constexpr int PG = NB == 1 ? A : 4;
   static_assert(A % PG == 0, "plane groups tile the planes");
   static constexpr int TNT = NT / PG;
+  using Sy = std::conditional_t<TNT == 64, WaveSync, BlockSync>;
   static constexpr int PAD = 1;           // three spare slots per 32
   static constexpr int SLOTS = pad_slots<PAD>(NY * NB);
   using L = Tile<NB, NB, 1, true, PAD>;
@@ -114,12 +119,13 @@ __global__ __launch_bounds__(kWideThreads) void k_faw(GroupArgs ga, const BoxRec
     auto st_tile = [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; };
     // the first planes' transforms pass a workgroup barrier after their first exchange write, so
     // that the twiddle table written by every wavefront is complete before its first read
+    using Sy = typename S::Sy;
     if (a0 == 0)
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, BlockSync, BlockSync>(mytile, TwS<T>{tw}, stid,
-                                                                                                 ld_plane, st_tile);
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy, BlockSync>(mytile, TwS<T>{tw}, stid,
+                                                                                          ld_plane, st_tile);
     else
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, BlockSync>(mytile, TwS<T>{tw}, stid, ld_plane,
-                                                                                    st_tile);
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, -1, false, true, 0, 1, Sy>(mytile, TwS<T>{tw}, stid, ld_plane,
+                                                                             st_tile);
     __syncthreads();
     // each lane separates its column of its positions from the Hermitian pairs and remaps them
 #pragma unroll
@@ -272,19 +278,20 @@ __global__ __launch_bounds__(kWideThreads) void k_fcw(GroupArgs ga, const BoxRec
         *reinterpret_cast<gmem<cplx<T>>*>(dst + (size_t)e * nz + 2 * cc) = v;
       }
     };
+    using Sy = typename S::Sy;
     if constexpr (LIN) {
       YInterp yi;
       yi.init(br->shy * (x + 0.5), NY);
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true, 0, 1, BlockSync>(
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, true, 0, 1, Sy>(
           mytile, TwS<T>{tw}, stid, [&](int e, int cc) { return mytile[L::at(e, cc)]; },
           [&](int e, int cc, cplx<T> v) { mytile[L::at(e, cc)] = v; });
-      __syncthreads();
+      Sy::sync();
       for (int w = stid; w < NY * NB; w += TNT) {
         const int cc = w % NB, e = w / NB;
         store(e, cc, yi.sample<T>(e, NY, [&](int y) { return mytile[L::at(y, cc)]; }));
       }
     } else {
-      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false, 0, 1, BlockSync>(
+      fft_run<T, NY, typename Fwd<NY>::L, L, TNT, +1, true, false, 0, 1, Sy>(
           mytile, TwS<T>{tw}, stid, [&](int e, int cc) { return mytile[L::at(e, cc)]; }, store);
     }
     __syncthreads();  // the tiles are rebuilt for the next planes

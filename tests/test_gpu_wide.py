@@ -6,7 +6,8 @@ block); by default they run five-pass, the faster on gfx950.  Every kernel shape
 schedule instantiates appears below: Ny = 512 and 1024, A = 8 and 16 (16-byte rows, and 8-byte
 rows at Ny = 1024 with A = 16), M = 64 to 512, VGF and SASHA, spectral and linear remap, direct
 launches and graph replay; then a plan that mixes a wide box with narrow fused and five-pass
-boxes, and the 1024 x 1024 x 256 clumpy box against the five-pass solve."""
+boxes, and two full-size boxes (the 1024 x 1024 x 256 clumpy box among them) against the five-pass
+solve."""
 
 import numpy as np
 import pytest
@@ -98,21 +99,28 @@ def test_wide_in_a_mixed_plan():
 
 
 @pytest.mark.timeout(300)
-def test_wide_clumpy_1024_against_five_pass():
-    # the 1024 x 1024 x 256 clumpy box (A = 16, Ny = 1024, M = 512) fused on request, element by
-    # element against the five-pass solve of the same input (which the full-size tests hold to the
-    # oracle cell by cell)
+@pytest.mark.parametrize("shape", [(1024, 1024, 256), (512, 1024, 256)], ids=["clumpy1024", "lognormal512x1024"])
+def test_wide_full_size_against_five_pass(shape):
+    # full-size boxes fused on request, element by element against the five-pass solve of the same
+    # input: the 1024 x 1024 x 256 clumpy box (A = 16, Ny = 1024, 8-byte rows, M = 512; the
+    # full-size tests hold its five-pass solve to the oracle cell by cell) and a 512 x 1024 x 256
+    # log-normal box (A = 8, 16-byte rows)
     import torch
 
     from paper_2510_10070_amd import Box, Plan, Shear
 
-    w = workload("clumpy-1024")
-    rho = torch.tensor(w["make"](), dtype=torch.float32, device="cuda:0")
+    if shape == (1024, 1024, 256):
+        w = workload("clumpy-1024")
+        b, shear, rho = w["box"], w["shear"], w["make"]()
+    else:
+        b, shear = shape + (8.0, 16.0, 4.0), (1.5, 1.0, 2.5, 1.0)
+        rho = lognormal_density(shape, 4.0, 1.0, seed=350)
+    rho = torch.tensor(rho, dtype=torch.float32, device="cuda:0")
     out = {}
     for sched in ("fused", "five_pass"):
-        plan = Plan(Box(*w["box"]), precision="fp32", schedule=sched)
+        plan = Plan(Box(*b), precision="fp32", schedule=sched)
         phi = torch.empty_like(rho)
-        plan.solve(rho, phi, Shear(*w["shear"]))
+        plan.solve(rho, phi, Shear(*shear))
         torch.cuda.synchronize()
         out[sched] = (plan.describe()["path"], phi.double().cpu().numpy())
         plan.close()
@@ -120,6 +128,6 @@ def test_wide_clumpy_1024_against_five_pass():
     assert out["fused"][0] == "fused-3pass" and out["five_pass"][0] == "streaming-5pass"
     got, ref = out["fused"][1], out["five_pass"][1]
     err, mp, pm = rel_l2(got, ref), max_pointwise_error(got, ref), per_mode_error(got, ref, zchunk=32)
-    print(f"clumpy-1024 fp32 fused vs five-pass: rel-L2 {err:.3e}, max pointwise {mp:.3e}, per-mode {pm:.3e}")
+    print(f"{shape} fp32 fused vs five-pass: rel-L2 {err:.3e}, max pointwise {mp:.3e}, per-mode {pm:.3e}")
     assert np.isfinite(got).all()
     assert err <= 2 * TOL and mp <= 2 * TOL and pm <= 2 * TOL, (err, mp, pm)
