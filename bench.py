@@ -163,7 +163,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding across GPUs is described in the design notes, not implemented)", file=sys.stderr)
         return 2
 
     if args.copy_mib:
