@@ -131,3 +131,25 @@ def test_wide_full_size_against_five_pass(shape):
     print(f"{shape} fp32 fused vs five-pass: rel-L2 {err:.3e}, max pointwise {mp:.3e}, per-mode {pm:.3e}")
     assert np.isfinite(got).all()
     assert err <= 2 * TOL and mp <= 2 * TOL and pm <= 2 * TOL, (err, mp, pm)
+
+
+@pytest.mark.parametrize("precision,shape,pad", [("fp64", (512, 512, 32), 2), ("fp32", (512, 512, 32), 4),
+                                                 ("fp32", (512, 256, 32), 2), ("fp32", (1024, 512, 512), 2)],
+                         ids=["fp64", "pad4", "ny256", "m1024"])
+def test_wide_request_outside_its_domain_runs_five_pass(precision, shape, pad):
+    # the fused request covers the wide boxes in FP32 with padding 2, Ny in {512, 1024} and
+    # M <= 512 only; any other box of that width runs five-pass under the same flag
+    from paper_2510_10070_amd import Box, Plan
+
+    box = dict(_box(shape, "vgf", "spectral", 1), pad=pad)
+    plan = Plan([Box(**box)], precision=precision, schedule="fused")
+    d = plan.describe()
+    plan.close()
+    assert d["path"] == "streaming-5pass", d
+    if shape[2] <= 32:  # small enough for the oracle here
+        rho = lognormal_density(shape, 1.0, 0.25, seed=360 + pad)
+        shear = (1.5, 1.0, 0.61, 1.0)
+        got, used = gpu_solve(box, rho, shear, precision, schedule="fused")
+        ref = oracle_solve(box, used[0], shear)
+        tol = 1e-12 if precision == "fp64" else TOL
+        assert rel_l2(got[0], ref) <= tol and max_pointwise_error(got[0], ref) <= tol
