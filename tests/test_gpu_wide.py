@@ -87,14 +87,20 @@ def test_wide_in_a_mixed_plan():
     wide = sorted((g["pass"], g["len"], g["boxes"]) for g in d["groups"] if g["variant"] == 4)
     assert wide == [("fused_a", 512, 1), ("fused_a", 1024, 1), ("fused_b", 64, 1), ("fused_b", 128, 1),
                     ("fused_c", 512, 1), ("fused_c", 1024, 1)], d
+    # the autotuner times the narrow box's tile variants and leaves the wide box's kernels alone
+    plan = Plan([Box(**b) for b in boxes], precision="fp32", schedule="fused", autotune=True)
+    dt = plan.describe()
+    plan.close()
+    assert dt["tuning"] in ("measured", "cache"), dt
+    assert sorted((g["pass"], g["len"], g["boxes"]) for g in dt["groups"] if g["variant"] == 4) == wide, dt
     rhos = [lognormal_density(s, 1.0, 0.2, seed=330 + k) for k, s in enumerate(shapes)]
     shears = [(1.5, 1.0, 0.2 + 0.15 * k, 1.0) for k in range(len(shapes))]
-    for graph in (False, True):
-        got, used = gpu_solve(boxes, rhos, shears, "fp32", schedule="fused", graph=graph)
+    for graph, tuned in ((False, False), (True, False), (False, True)):
+        got, used = gpu_solve(boxes, rhos, shears, "fp32", schedule="fused", graph=graph, autotune=tuned)
         for b, g, u, s in zip(boxes, got, used, shears):
             ref = oracle_solve(b, u, s)
             err, pm = rel_l2(g, ref), per_mode_error(g, ref)
-            print(f"{b['nx']}x{b['ny']}x{b['nz']} {b['method']} graph={graph}: {err:.2e} {pm:.2e}")
+            print(f"{b['nx']}x{b['ny']}x{b['nz']} {b['method']} graph={graph} tuned={tuned}: {err:.2e} {pm:.2e}")
             assert err <= TOL and pm <= TOL, b
 
 
