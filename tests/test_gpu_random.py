@@ -3,7 +3,8 @@
 Each case draws a box (every axis from the lengths the ABI accepts, kept small enough for the
 oracle), the padding and truncation, the method, the remap, the precision, the shear parameters
 and the launch mode (direct or graph-replayed, fused or five-pass by default); a few cases hold
-several boxes at once, and a second draw holds only plans of 2 to 8 boxes.  The draws are fixed
+several boxes at once, a second draw holds only plans of 2 to 8 boxes, and a third wide FP32 boxes
+(Nx, Ny in {512, 1024}) fused on request, alone or beside a box of the first draw.  The draws are fixed
 (seeds below), so a failure names a reproducible case."""
 
 import numpy as np
@@ -84,4 +85,31 @@ BATCH_CASES = _batch_cases()
 
 @pytest.mark.parametrize("case", BATCH_CASES, ids=[f"batch{i}" for i in range(len(BATCH_CASES))])
 def test_random_batch_plan(case):
+    test_random_plan(case)
+
+
+def _wide_cases():
+    # wide FP32 boxes fused on request (B = 64), each with a random partner box of the main draw
+    # in the same plan half of the time: Nx, Ny in {512, 1024}, M = 64 or 128
+    rng = np.random.default_rng(SEED + 2)
+    out = []
+    for _ in range(12):
+        nx, ny = int(rng.choice([512, 1024])), int(rng.choice([512, 1024]))
+        nz = 32 if nx * ny > 512 * 512 else int(rng.choice([32, 64]))
+        wide = dict(nx=nx, ny=ny, nz=nz, lx=float(rng.uniform(0.5, 3.0)), ly=float(rng.uniform(0.5, 3.0)),
+                    lz=float(rng.uniform(0.5, 2.0)), pad=2, alpha=0.0, method=str(rng.choice(["vgf", "sasha"])),
+                    remap=str(rng.choice(["spectral", "spectral", "linear"])))
+        boxes = [wide] + ([_draw_box(rng)] if rng.random() < 0.5 else [])
+        shears = [(float(rng.choice([1.5, 2.0])), float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.0, 3.0)),
+                   float(rng.uniform(0.2, 2.0))) for _ in boxes]
+        out.append(dict(boxes=boxes, shears=shears, precision="fp32", graph=bool(rng.random() < 0.3),
+                        schedule="fused", seed=int(rng.integers(0, 2**31))))
+    return out
+
+
+WIDE_CASES = _wide_cases()
+
+
+@pytest.mark.parametrize("case", WIDE_CASES, ids=[f"wide{i}" for i in range(len(WIDE_CASES))])
+def test_random_wide_plan(case):
     test_random_plan(case)
