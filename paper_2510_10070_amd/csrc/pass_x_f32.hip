@@ -10,8 +10,8 @@ hipError_t launch_x_impl<float>(int dir, int nx, int variant, GroupArgs ga, int 
   const dim3 grid(blocks);
   const cplx<T>* t = static_cast<const cplx<T>*>(tw);
 #define SBP_LAUNCH(N_, V_)                                                                     \
-  if (dir < 0) hipLaunchKernelGGL((k_x<T, N_, V_, -1>), grid, dim3(xy_threads<N_>()), 0, st, ga, recs, t);      \
-  else hipLaunchKernelGGL((k_x<T, N_, V_, +1>), grid, dim3(xy_threads<N_>()), 0, st, ga, recs, t);
+  if (dir < 0) hipLaunchKernelGGL((k_x<T, N_, V_, -1>), grid, dim3(x_threads<T, N_, V_>()), 0, st, ga, recs, t);      \
+  else hipLaunchKernelGGL((k_x<T, N_, V_, +1>), grid, dim3(x_threads<T, N_, V_>()), 0, st, ga, recs, t);
 #define SBP_CASE(N_)                  \
   if (nx == N_) {                     \
     if (variant) { SBP_LAUNCH(N_, 1) } \

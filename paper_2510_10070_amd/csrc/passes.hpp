@@ -93,10 +93,14 @@ template <typename T, int N, int V> constexpr int y_zc() {
   constexpr int big = sizeof(T) == 4 ? (N <= 512 ? 32 : 16) : (N <= 512 ? 16 : 8);
   return V ? big : big / 2;
 }
-// x: complex z cells per tile
+// x: complex z cells per tile; float transforms of 1024 points take 128-byte rows in variant 1,
+// whose 128 KB tile leaves room for one block per CU, made of 1024 threads
 template <typename T, int N, int V> constexpr int x_zc() {
-  constexpr int big = sizeof(T) == 4 ? (N <= 512 ? 16 : 8) : (N <= 512 ? 8 : 4);
+  constexpr int big = sizeof(T) == 4 ? (N <= 512 || (N == 1024 && V) ? 16 : 8) : (N <= 512 ? 8 : 4);
   return V ? big : big / 2;
+}
+template <typename T, int N, int V> constexpr int x_threads() {
+  return (sizeof(T) == 4 && N == 1024 && V == 1) ? 1024 : xy_threads<N>();
 }
 // z: pencils one wavefront transforms side by side (about eight points per lane), pencils per
 // wavefront (variant 1: four such groups, variant 0: two; at most 64), pencils per block
@@ -393,10 +397,10 @@ __global__ __launch_bounds__(xy_threads<NY>()) void k_yinv(GroupArgs ga, const B
 // x: one block per (my, chunk of ZC consecutive z cells); rows of ZC contiguous complex values.
 
 template <typename T, int NX, int V, int D>
-__global__ __launch_bounds__(xy_threads<NX>()) void k_x(GroupArgs ga, const BoxRec* __restrict__ recs,
-                                                    const cplx<T>* __restrict__ twg) {
+__global__ __launch_bounds__((x_threads<T, NX, V>())) void k_x(GroupArgs ga, const BoxRec* __restrict__ recs,
+                                                            const cplx<T>* __restrict__ twg) {
   constexpr int ZC = x_zc<T, NX, V>();
-  constexpr int NT = xy_threads<NX>();
+  constexpr int NT = x_threads<T, NX, V>();
   constexpr int PAD = sizeof(T) == 4 ? 1 : 0;  // float: three spare slots per 32 (bank conflicts)
   using L = Tile<ZC, ZC, 1, true, PAD>;
   __shared__ cplx<T> buf[pad_slots<PAD>(NX * ZC)];
